@@ -1,0 +1,148 @@
+"""Python access to the plain FP64 CPU oracle (oracle/mgr_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg import this package; the GPU product path never
+does.  Every function works on float64 NumPy arrays and returns a new array
+(the C library transforms a private copy in place).
+
+What each function computes is documented in oracle/mgr_oracle.c, with the
+paper passages (Sec. II-A, Eq. (1)-(2), Sec. III-A) that it follows.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_ERRORS = {1: "argument", 2: "shape", 3: "levels", 4: "coordinates", 6: "allocation"}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        dpp = ctypes.POINTER(dp)
+        for name in ("oracle_decompose", "oracle_recompose", "oracle_decompose_adjoint"):
+            fn = getattr(lib, name)
+            fn.argtypes = [dp, ctypes.c_int, i64p, dpp, ctypes.c_int]
+            fn.restype = ctypes.c_int
+        lib.oracle_max_levels.argtypes = [ctypes.c_int, i64p]
+        lib.oracle_max_levels.restype = ctypes.c_int
+        lib.oracle_coefficients_level.argtypes = [dp, ctypes.c_int, i64p, dpp, ctypes.c_int]
+        lib.oracle_coefficients_level.restype = ctypes.c_int
+        lib.oracle_load_vector_level.argtypes = [dp, dp, ctypes.c_int, i64p, dpp, ctypes.c_int]
+        lib.oracle_load_vector_level.restype = ctypes.c_int
+        lib.oracle_correction_level.argtypes = [dp, ctypes.c_int, i64p, dpp, ctypes.c_int]
+        lib.oracle_correction_level.restype = ctypes.c_int
+        lib.oracle_class_map.argtypes = [ctypes.c_int, i64p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint8)]
+        lib.oracle_class_map.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _shape_arg(shape):
+    arr = (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+    return arr
+
+
+def _coords_arg(shape, coords):
+    """Returns (ctypes double** or None, keep-alive list)."""
+    if coords is None:
+        return None, []
+    keep = []
+    ptrs = (ctypes.POINTER(ctypes.c_double) * len(shape))()
+    for d, c in enumerate(coords):
+        if c is None:
+            ptrs[d] = ctypes.POINTER(ctypes.c_double)()
+            continue
+        a = np.ascontiguousarray(c, dtype=np.float64)
+        if a.shape != (shape[d],):
+            raise ValueError(f"coords[{d}] must have length {shape[d]}")
+        keep.append(a)
+        ptrs[d] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))), keep
+
+
+def _check(rc):
+    if rc != 0:
+        raise OracleError(f"oracle error {rc} ({_ERRORS.get(rc, '?')})")
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def max_levels(shape):
+    return _load().oracle_max_levels(len(shape), _shape_arg(shape))
+
+
+def _run(name, u, coords, nlevels):
+    lib = _load()
+    a = np.array(u, dtype=np.float64, order="C", copy=True)
+    cp, keep = _coords_arg(a.shape, coords)
+    _check(getattr(lib, name)(_dp(a), a.ndim, _shape_arg(a.shape), cp, int(nlevels)))
+    del keep
+    return a
+
+
+def decompose(u, coords=None, nlevels=-1):
+    """Multilevel decomposition (Sec. II-A, Eq. (1)-(2)) in FP64."""
+    return _run("oracle_decompose", u, coords, nlevels)
+
+
+def recompose(u, coords=None, nlevels=-1):
+    """Exact inverse of decompose (Sec. II-A, recomposition)."""
+    return _run("oracle_recompose", u, coords, nlevels)
+
+
+def decompose_adjoint(g, coords=None, nlevels=-1):
+    """Transpose of decompose under the Euclidean inner product."""
+    return _run("oracle_decompose_adjoint", g, coords, nlevels)
+
+
+def coefficients_level(u, k, coords=None):
+    """Coefficient stage of level step k only (Sec. II-A.1)."""
+    return _run("oracle_coefficients_level", u, coords, k)
+
+
+def load_vector_level(u, k, coords=None):
+    """Load vector f = R M vec(C) of level step k, packed (Sec. II-A.2)."""
+    lib = _load()
+    a = np.ascontiguousarray(u, dtype=np.float64)
+    cshape = tuple(((n - 1) >> (k + 1)) + 1 for n in a.shape)
+    f = np.zeros(cshape, dtype=np.float64)
+    cp, keep = _coords_arg(a.shape, coords)
+    _check(lib.oracle_load_vector_level(_dp(a), _dp(f), a.ndim, _shape_arg(a.shape), cp, int(k)))
+    del keep
+    return f
+
+
+def correction_level(f, shape, k, coords=None):
+    """Solves M_{l-1} z = f for level step k (Sec. II-A.2); f packed."""
+    lib = _load()
+    z = np.array(f, dtype=np.float64, order="C", copy=True)
+    cp, keep = _coords_arg(tuple(shape), coords)
+    _check(lib.oracle_correction_level(_dp(z), len(shape), _shape_arg(shape), cp, int(k)))
+    del keep
+    return z
+
+
+def class_map(shape, nlevels=-1):
+    """Coefficient class of every node (0 = coarsest values, L = finest)."""
+    lib = _load()
+    out = np.zeros(tuple(shape), dtype=np.uint8)
+    _check(lib.oracle_class_map(len(shape), _shape_arg(shape), int(nlevels),
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return out

@@ -1,0 +1,25 @@
+"""Builds the CPU oracle library (oracle/liboracle.so) with gcc.
+
+Test infrastructure only: the oracle is used by the test suite, the smoke
+check and the benchmark's CPU-baseline leg, never by the GPU product path.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(HERE, "mgr_oracle.c")
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", LIB + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,311 @@
+"""Pins of the CPU oracle to things other than itself (CPU only).
+
+Each test names the passage or the mathematics it checks.  A plausible
+mistake anywhere in the oracle (a dropped term, a swapped interpolation
+weight, a wrong boundary row, a transposed operand, a wrong sweep order)
+fails at least one of them:
+  - dense L2 projections (every output element, tiny grids),
+  - exact zero coefficients for multilinear input (bitwise, dyadic data),
+  - the paper's 1D quadratic example (closed form),
+  - 1D closed forms of the load-vector stencil and the correction solve,
+  - recompose(decompose(x)) = x and progressive recomposition,
+  - scale invariance of the coordinates (bitwise),
+  - the adjoint against the explicit dense transpose, a dot-product test and
+    exact central finite differences of a quadratic loss.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import dense_ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_coords(rng, shape):
+    out = []
+    for n in shape:
+        h = rng.uniform(0.5, 1.5, n - 1)
+        x = np.concatenate([[0.0], np.cumsum(h)])
+        out.append(x / x[-1])
+    return out
+
+
+TINY = [(9,), (17,), (33,), (9, 9), (17, 9), (5, 17), (5, 5, 5), (9, 5, 9), (9, 9, 9)]
+
+
+@pytest.mark.parametrize("shape", TINY)
+@pytest.mark.parametrize("nonuniform", [False, True])
+def test_matches_dense_l2_projection(shape, nonuniform):
+    """Eq. (1)-(2): coarsest = Q_0 u, class l = (I - Pi_{l-1}) Q_l u."""
+    rng = np.random.default_rng(hash((shape, nonuniform)) % 2**32)
+    coords = rand_coords(rng, shape) if nonuniform else None
+    u = rng.standard_normal(shape)
+    full = oracle.max_levels(shape)
+    for L in sorted({1, full, full + 1}):
+        if L < 1:
+            continue
+        got = oracle.decompose(u, coords, L)
+        want = dense_ref.decompose_dense(u, coords, L)
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(u)), (shape, L)
+
+
+def test_dense_reference_is_an_l2_projection():
+    """Orthogonality (Sec. II-A.2): the detail Q_l u - Q_{l-1} u is
+    M-orthogonal to V_{l-1}; checks the dense reference itself."""
+    rng = np.random.default_rng(11)
+    shape = (9, 5)
+    coords = rand_coords(rng, shape)
+    u = rng.standard_normal(shape)
+    L = 2
+    xs = [c for c in coords]
+    M_L = dense_ref.kron_all([dense_ref.fe_mass_1d(x) for x in xs])
+    for l in (1, 2):
+        q = dense_ref.projection_values(u, coords, L, l)
+        qc = dense_ref.projection_values(u, coords, L, l - 1)
+        Bl = dense_ref.kron_all([dense_ref.hat_eval_1d(x, x[:: 2 ** (L - l)]) for x in xs])
+        Bc = dense_ref.kron_all([dense_ref.hat_eval_1d(x, x[:: 2 ** (L - l + 1)]) for x in xs])
+        detail = Bl @ q.reshape(-1) - Bc @ qc.reshape(-1)
+        # orthogonal to every coarse basis function
+        assert np.max(np.abs(Bc.T @ (M_L @ detail))) < 1e-13
+        # and u - Q_l u orthogonal to V_l
+        r = u.reshape(-1) - Bl @ q.reshape(-1)
+        assert np.max(np.abs(Bl.T @ (M_L @ r))) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(33,), (17, 9), (9, 17, 5), (17, 17, 17)])
+def test_multilinear_input_gives_exact_zero_classes(shape):
+    """Sec. II-A.1: coefficients vanish where u is already multilinear.  With
+    integer coarse data on a uniform grid the arithmetic is exact, so classes
+    finer than the data's level are zero bitwise and the values at the data's
+    nodes pass through unchanged."""
+    rng = np.random.default_rng(3)
+    L = oracle.max_levels(shape)
+    for j in range(1, L + 1):  # data live on the grid of stride 2^j
+        s = 2 ** j
+        coarse = rng.integers(-8, 9, tuple((n - 1) // s + 1 for n in shape)).astype(np.float64)
+        # multilinear interpolant on the finest grid, by repeated 1D averaging
+        u = coarse
+        for d in range(len(shape)):
+            for _ in range(j):
+                m = u.shape[d]
+                new_shape = list(u.shape)
+                new_shape[d] = 2 * m - 1
+                v = np.zeros(new_shape)
+                sl_even = [slice(None)] * len(shape)
+                sl_even[d] = slice(0, None, 2)
+                v[tuple(sl_even)] = u
+                lo = [slice(None)] * len(shape)
+                hi = [slice(None)] * len(shape)
+                od = [slice(None)] * len(shape)
+                lo[d], hi[d], od[d] = slice(0, m - 1), slice(1, m), slice(1, None, 2)
+                v[tuple(od)] = 0.5 * (u[tuple(lo)] + u[tuple(hi)])
+                u = v
+        out = oracle.decompose(u, None, L)
+        cls = oracle.class_map(shape, L)
+        assert np.all(out[cls > L - j] == 0.0), (shape, j)
+        # the first L-j levels leave the stride-2^j values untouched
+        part = oracle.decompose(u, None, j)
+        sl = tuple(slice(None, None, s) for _ in shape)
+        assert np.array_equal(part[sl], u[sl])
+
+
+def test_paper_quadratic_example():
+    """Sec. II-A.1, Fig. 2: y = x^2 - 5x + 6; finest coefficients = -h^2."""
+    data = np.loadtxt(os.path.join(GOLDEN, "fig2_quadratic_1d.txt"))
+    x, y, c = data[:, 0], data[:, 1], data[:, 2]
+    out = oracle.decompose(y, [x], 3)
+    odd = ~np.isnan(c)
+    assert np.array_equal(out[odd], c[odd])
+    # one step only: the level step of the finest grid gives the same values
+    one = oracle.decompose(y, [x], 1)
+    assert np.array_equal(one[odd], c[odd])
+
+
+def test_load_vector_uniform_stencil():
+    """Sec. III-A.2: on a uniform grid (h = 1) R M applied to a unit value at
+    an odd node 2i+1 gives 3 at coarse nodes i and i+1; at an interior even
+    fine node (possible only in >= 2D, so tested via the 1D operator on the
+    even-node coefficient-free pattern) the merged stencil is (1/2, 3, 5, 3,
+    1/2).  Here the 1D load vector of single odd spikes is checked."""
+    n = 17
+    for j in range(1, n, 2):
+        u = np.zeros(n)
+        u[j] = 1.0
+        f = oracle.load_vector_level(u, 0)
+        want = np.zeros((n + 1) // 2)
+        i = (j - 1) // 2
+        want[i] = 3.0
+        want[i + 1] = 3.0
+        assert np.array_equal(f, want), j
+
+
+def test_load_vector_2d_even_row_stencil():
+    """Along an axis, R M maps a unit value at an even interior node 2i to
+    (1/2, 5, 1/2) at coarse nodes (i-1, i, i+1) (uniform h = 1); in 2D a
+    value at (odd, even) therefore gives the outer product of (3, 3) and
+    (1/2, 5, 1/2)."""
+    shape = (9, 17)
+    u = np.zeros(shape)
+    u[3, 8] = 1.0
+    f = oracle.load_vector_level(u, 0)
+    want = np.zeros((5, 9))
+    want[1:3, 3:6] = np.outer([3.0, 3.0], [0.5, 5.0, 0.5])
+    assert np.array_equal(f, want)
+
+
+@pytest.mark.parametrize("nonuniform", [False, True])
+def test_correction_is_textbook_banded_solve(nonuniform):
+    """Sec. II-A.2: z solves M_{l-1} z = f; compare with scipy's banded LU on
+    the finite-element mass matrix (scaled by 6) of the coarse coordinates."""
+    rng = np.random.default_rng(5)
+    n = 33
+    coords = rand_coords(rng, (n,)) if nonuniform else None
+    x = coords[0] if nonuniform else np.arange(n, dtype=np.float64)
+    for k in range(0, 4):
+        xc = x[:: 2 ** (k + 1)]
+        f = rng.standard_normal(len(xc))
+        z = oracle.correction_level(f, (n,), k, coords)
+        M = 6.0 * dense_ref.fe_mass_1d(xc)
+        ab = np.zeros((3, len(xc)))
+        ab[0, 1:] = np.diag(M, 1)
+        ab[1] = np.diag(M)
+        ab[2, :-1] = np.diag(M, -1)
+        want = scipy.linalg.solve_banded((1, 1), ab, f)
+        assert np.max(np.abs(z - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("shape", [(65,), (33, 17), (17, 9, 33), (33, 33, 33)])
+@pytest.mark.parametrize("nonuniform", [False, True])
+def test_roundtrip(shape, nonuniform):
+    """Sec. II-A: recomposition is the exact inverse of decomposition."""
+    rng = np.random.default_rng(7)
+    coords = rand_coords(rng, shape) if nonuniform else None
+    u = rng.standard_normal(shape)
+    for L in (1, oracle.max_levels(shape), oracle.max_levels(shape) + 1):
+        d = oracle.decompose(u, coords, L)
+        r = oracle.recompose(d, coords, L)
+        assert np.max(np.abs(r - u)) <= 1e-13 * np.max(np.abs(u))
+
+
+@pytest.mark.parametrize("shape", [(17,), (9, 17), (9, 5, 9)])
+def test_progressive_recomposition(shape):
+    """Sec. I and II-A: recomposing from the classes 0..l0 only returns the
+    projection Q_{l0} u, interpolated to the finest nodes."""
+    rng = np.random.default_rng(9)
+    coords = rand_coords(rng, shape)
+    u = rng.standard_normal(shape)
+    L = oracle.max_levels(shape)
+    d = oracle.decompose(u, coords, L)
+    cls = oracle.class_map(shape, L)
+    for l0 in range(0, L + 1):
+        trunc = np.where(cls <= l0, d, 0.0)
+        r = oracle.recompose(trunc, coords, L)
+        want = dense_ref.progressive_dense(u, coords, L, l0)
+        assert np.max(np.abs(r - want)) <= 1e-12 * np.max(np.abs(u)), l0
+
+
+def test_scale_invariance_bitwise():
+    """Only coordinate ratios enter the method: scaling all coordinates by a
+    power of two, or replacing None by i * 2^-k, changes no bit."""
+    rng = np.random.default_rng(13)
+    shape = (17, 9, 33)
+    u = rng.standard_normal(shape)
+    coords = rand_coords(rng, shape)
+    a = oracle.decompose(u, coords)
+    b = oracle.decompose(u, [c * 8.0 for c in coords])
+    assert np.array_equal(a, b)
+    c = oracle.decompose(u, None)
+    e = oracle.decompose(u, [np.arange(n) / (n - 1) for n in shape])
+    assert np.array_equal(c, e)
+    f = oracle.decompose(u, [None, np.arange(9) * 0.25, None])
+    assert np.array_equal(c, f)
+
+
+def test_class_map_definition():
+    """Class of a node: 0 for the coarsest nodes, else L minus the smallest
+    2-adic valuation of its indices (brute force)."""
+    shape = (17, 9, 5)
+    L = 2
+    cm = oracle.class_map(shape, L)
+    for idx in np.ndindex(*shape):
+        v = L
+        for i in idx:
+            if i == 0:
+                continue
+            t = 0
+            while i % 2 == 0:
+                i //= 2
+                t += 1
+            v = min(v, t)
+        assert cm[idx] == (0 if v >= L else L - v)
+
+
+def test_adjoint_equals_dense_transpose():
+    """The transposed map equals the transpose of the dense decomposition
+    matrix built from the L2 projections (9x9x9 grid, 729 unit vectors)."""
+    rng = np.random.default_rng(17)
+    for shape, nonuni in [((9, 9, 9), False), ((9, 5, 9), True), ((17, 9), True), ((33,), True)]:
+        coords = rand_coords(rng, shape) if nonuni else None
+        L = oracle.max_levels(shape)
+        D = dense_ref.decompose_matrix(shape, coords, L)
+        g = rng.standard_normal(shape)
+        got = oracle.decompose_adjoint(g, coords, L)
+        want = (D.T @ g.reshape(-1)).reshape(shape)
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)), shape
+
+
+@pytest.mark.parametrize("shape", [(17, 17, 17), (33, 9, 17), (65, 33)])
+def test_adjoint_dot_product(shape):
+    """<D x, g> = <x, D^T g> for random x, g."""
+    rng = np.random.default_rng(19)
+    coords = rand_coords(rng, shape)
+    x = rng.standard_normal(shape)
+    g = rng.standard_normal(shape)
+    lhs = np.sum(oracle.decompose(x, coords) * g)
+    rhs = np.sum(x * oracle.decompose_adjoint(g, coords))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.sqrt(x.size))
+
+
+def test_adjoint_finite_difference_17cubed():
+    """Loss = sum_l 2^l ||class l||^2 is quadratic in x, so its central
+    difference is exact up to rounding; compare with <grad, e> where
+    grad = D^T (2 w * D x)."""
+    rng = np.random.default_rng(6)
+    shape = (17, 17, 17)
+    x = rng.standard_normal(shape)
+    L = oracle.max_levels(shape)
+    w = np.power(2.0, oracle.class_map(shape, L))
+
+    def loss(v):
+        d = oracle.decompose(v, None, L)
+        return np.sum(w * d * d)
+
+    grad = oracle.decompose_adjoint(2.0 * w * oracle.decompose(x, None, L), None, L)
+    for t in range(4):
+        e = rng.standard_normal(shape)
+        eps = 1e-3
+        fd = (loss(x + eps * e) - loss(x - eps * e)) / (2 * eps)
+        an = np.sum(grad * e)
+        assert abs(fd - an) <= 1e-9 * abs(an), t
+
+
+def test_error_codes():
+    u = np.zeros((9, 9))
+    with pytest.raises(oracle.OracleError, match="shape"):
+        oracle.decompose(np.zeros((10, 9)))
+    with pytest.raises(oracle.OracleError, match="shape"):
+        oracle.decompose(np.zeros((2, 9)))
+    with pytest.raises(oracle.OracleError, match="levels"):
+        oracle.decompose(u, None, 4)
+    with pytest.raises(oracle.OracleError, match="coordinates"):
+        oracle.decompose(u, [np.array([0, 1, 2, 3, 3, 5, 6, 7, 8.0]), None])
+    assert oracle.max_levels((9, 9)) == 2
+    assert oracle.max_levels((513, 513, 513)) == 8
+    assert oracle.max_levels((1025, 1025, 257)) == 7
+    # nlevels = 0 is the identity
+    v = np.arange(81.0).reshape(9, 9)
+    assert np.array_equal(oracle.decompose(v, None, 0), v)
