@@ -1,0 +1,130 @@
+/*
+ * mgr.h - C ABI of libmgr, the MI355X (gfx950) implementation of multigrid
+ * hierarchical data refactoring (Chen et al., "Accelerating Multigrid-based
+ * Hierarchical Scientific Data Refactoring on GPUs", arXiv 2007.04457).
+ *
+ * Data model (shared by every entry point)
+ * -----------------------------------------
+ *  - A field is a C-order array of `prod(shape)` elements of type `dtype`
+ *    in device memory (HBM), `ndim` in 1..3, `shape[d] = 2^k_d + 1` with
+ *    k_d >= 1 (the structured grids of Sec. II-A; shape[ndim-1] is the
+ *    contiguous dimension).
+ *  - `coords` describes node positions (nonuniform structured grids,
+ *    Sec. II-A): NULL, or coords[d] == NULL, means uniform spacing along d;
+ *    otherwise coords[d] is a HOST array of shape[d] strictly increasing
+ *    doubles.  Only ratios of spacings matter.  The library reads them
+ *    during the call only.
+ *  - `nlevels` is the number of level steps L.  -1 selects the full
+ *    decomposition, L = min_d k_d - 1, whose coarsest grid has 3 nodes along
+ *    the shortest dimension; 0..min_d k_d are accepted (0 = identity copy).
+ *    All dimensions coarsen together.
+ *  - Refactored layout ("in-place node order", the same-shaped refactored
+ *    grid of Sec. II-A, overall process): element i of the output belongs to
+ *    node i.  Nodes whose indices are all multiples of 2^L hold the
+ *    coarsest nodal values (class 0); any other node, with v the smallest
+ *    2-adic valuation of its indices, holds its level coefficient (class
+ *    L - v, L = finest).  mgr_class_map returns this class map.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every GPU
+ *    entry point only enqueues work on it and returns; results are ready
+ *    when the stream reaches that point.
+ *  - `src` and `dst` are caller-owned device pointers of the same size;
+ *    dst == src is allowed (in place); other overlaps are not.
+ *  - The library owns its tables and workspace (device memory, cached per
+ *    problem; released by mgr_finalize).  Calls that share a problem
+ *    (dtype, shape, coords, nlevels) share its workspace, so they must be
+ *    ordered on one stream.
+ *
+ * Errors: every int-returning function returns MGR_OK (0) or a positive
+ * status; arguments are validated before anything is enqueued, no
+ * exception crosses the ABI, and mgr_last_error() gives a detail string.
+ */
+#ifndef MGR_H
+#define MGR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { MGR_F32 = 0, MGR_F64 = 1 } mgr_dtype;
+
+enum {
+    MGR_OK = 0,
+    MGR_ERR_ARG = 1,      /* null pointer, bad ndim or dtype */
+    MGR_ERR_SHAPE = 2,    /* a size is not 2^k + 1 with k >= 1 */
+    MGR_ERR_LEVELS = 3,   /* nlevels outside -1, 0..min_d k_d */
+    MGR_ERR_COORDS = 4,   /* coordinates not strictly increasing or not finite */
+    MGR_ERR_HIP = 5,      /* a HIP runtime call or kernel launch failed */
+    MGR_ERR_ALLOC = 6,    /* device allocation failed or exceeds MGR_WORKSPACE_MAX */
+    MGR_ERR_CAPTURE = 7   /* would allocate while `stream` is being captured */
+};
+
+/* Full level count for a shape (min_d k_d - 1), or minus a status. */
+int mgr_max_levels(int ndim, const int64_t* shape);
+
+/* Decomposition (refactoring), Sec. II-A, Eq. (1)-(2): for each level step,
+ * finest first, the coefficients (I - Pi_{l-1}) Q_l u at the fine-only nodes
+ * (multilinear interpolation from the coarse nodes, Sec. II-A.1), the load
+ * vector f = R M vec(C) and the correction solve M_{l-1} z = f along every
+ * dimension (Sec. II-A.2, Sec. III-A), and z added to the coarse nodes.
+ * Reads src, writes the refactored layout to dst. */
+int mgr_decompose(const void* src, void* dst, int dtype, int ndim,
+                  const int64_t* shape, const double* const* coords,
+                  int nlevels, void* stream);
+
+/* Recomposition: the exact inverse of mgr_decompose, coarsest level first
+ * (Sec. II-A, overall process). Reads a refactored array from src. */
+int mgr_recompose(const void* src, void* dst, int dtype, int ndim,
+                  const int64_t* shape, const double* const* coords,
+                  int nlevels, void* stream);
+
+/* Adjoint (transpose) of mgr_decompose under the Euclidean inner product of
+ * the arrays: dst = D^T src.  Derived from Eq. (1)-(2); not in the paper.
+ * Per level step, coarse to fine: y = M_{l-1}^{-1} g_c (tridiagonal solves),
+ * t = (M P) y (transposed load-vector stencil), out_f = g_f + t at the
+ * fine-only nodes, out_c = g_c - Pi^T out_f. */
+int mgr_decompose_adjoint(const void* src, void* dst, int dtype, int ndim,
+                          const int64_t* shape, const double* const* coords,
+                          int nlevels, void* stream);
+
+/* Builds and uploads the tables and allocates the workspace of a problem
+ * (synchronously), so that later calls on a capturing stream allocate
+ * nothing.  Optional: the compute entry points prepare on first use. */
+int mgr_prepare(int dtype, int ndim, const int64_t* shape,
+                const double* const* coords, int nlevels);
+
+/* Writes the class id of every node (uint8, C order) to host memory out. */
+int mgr_class_map(int ndim, const int64_t* shape, int nlevels, uint8_t* out);
+
+/* Human-readable name of a status code (static storage). */
+const char* mgr_status_string(int status);
+
+/* Detail of the last error on the calling thread (empty if none). */
+const char* mgr_last_error(void);
+
+/* Frees every cached table, workspace and timing event.  Not safe while
+ * work that uses them is still in flight: synchronise first. */
+void mgr_finalize(void);
+
+/* ---- measurement support ------------------------------------------------
+ * The single-pass copy kernel the paper uses to define achievable
+ * bandwidth (Sec. IV-C): dst[i] = src[i] for nbytes (a multiple of 16,
+ * 16-byte aligned pointers). */
+int mgr_bench_copy(const void* src, void* dst, size_t nbytes, void* stream);
+
+/* Kernel timing: when enabled, every launch of kernel class `kernel` at
+ * level step `level` (0 = finest) is bracketed by HIP events on the stream
+ * it is launched on.  mgr_timing_read synchronises those events and returns
+ * the summed duration (ms) and launch count since the last reset.
+ * Kernel classes are listed by mgr_kernel_name(0..). */
+int mgr_timing_enable(int kernel, int level);
+int mgr_timing_disable(void);
+int mgr_timing_read(double* total_ms, int64_t* launches);
+const char* mgr_kernel_name(int kernel);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,207 @@
+"""Multigrid hierarchical data refactoring on MI355X (gfx950).
+
+Implements the multilevel decomposition of Chen et al., "Accelerating
+Multigrid-based Hierarchical Scientific Data Refactoring on GPUs" (arXiv
+2007.04457, Sec. II-A), its inverse and its adjoint, as HIP kernels behind the
+C ABI of include/mgr.h.  This package is a thin binding: tensors must be
+contiguous float32/float64 CUDA (HIP) tensors; torch supplies device memory
+and the current stream, the library does all the arithmetic.
+
+The C entry points are exposed under their own names (``mgr_decompose`` ...,
+taking ``src`` and ``dst`` tensors), with out-of-place conveniences
+(``decompose`` ...) and an autograd function (``Decompose``).
+"""
+from . import _lib
+from ._lib import MgrError, MGR_F32, MGR_F64
+
+__all__ = [
+    "MgrError", "MGR_F32", "MGR_F64",
+    "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_prepare",
+    "mgr_class_map", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize",
+    "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
+    "decompose", "recompose", "decompose_adjoint", "Decompose", "kernel_classes",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return MGR_F32
+    if t.dtype == torch.float64:
+        return MGR_F64
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _check(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _call(fn_name, src, dst, coords, nlevels):
+    _check(src, "src")
+    _check(dst, "dst")
+    if src.shape != dst.shape or src.dtype != dst.dtype or src.device != dst.device:
+        raise ValueError("src and dst must have the same shape, dtype and device")
+    lib = _lib.load()
+    torch = _torch()
+    cp, keep = _lib.coords_arg(tuple(src.shape), coords)
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    with torch.cuda.device(src.device):
+        st = getattr(lib, fn_name)(src.data_ptr(), dst.data_ptr(), _dtype_code(src), src.dim(),
+                                   _lib.shape_arg(src.shape), cp, int(nlevels), stream)
+    del keep
+    _lib.check(st)
+    return dst
+
+
+def mgr_decompose(src, dst, coords=None, nlevels=-1):
+    """dst <- decomposition of src (dst may be src).  See include/mgr.h."""
+    return _call("mgr_decompose", src, dst, coords, nlevels)
+
+
+def mgr_recompose(src, dst, coords=None, nlevels=-1):
+    """dst <- recomposition of the refactored array src."""
+    return _call("mgr_recompose", src, dst, coords, nlevels)
+
+
+def mgr_decompose_adjoint(src, dst, coords=None, nlevels=-1):
+    """dst <- D^T src, the transpose of the decomposition."""
+    return _call("mgr_decompose_adjoint", src, dst, coords, nlevels)
+
+
+def mgr_prepare(dtype, shape, coords=None, nlevels=-1):
+    """Builds tables and workspace ahead of time (before graph capture)."""
+    code = _dtype_code(_torch().empty(0, dtype=dtype)) if not isinstance(dtype, int) else dtype
+    lib = _lib.load()
+    cp, keep = _lib.coords_arg(tuple(shape), coords)
+    st = lib.mgr_prepare(code, len(shape), _lib.shape_arg(shape), cp, int(nlevels))
+    del keep
+    _lib.check(st)
+
+
+def mgr_max_levels(shape):
+    r = _lib.load().mgr_max_levels(len(shape), _lib.shape_arg(shape))
+    if r < 0:
+        _lib.check(-r)
+    return r
+
+
+def mgr_class_map(shape, nlevels=-1):
+    """Class id of every node as a NumPy uint8 array (0 = coarsest)."""
+    import ctypes
+    import numpy as np
+    out = np.zeros(tuple(int(s) for s in shape), dtype=np.uint8)
+    lib = _lib.load()
+    _lib.check(lib.mgr_class_map(len(shape), _lib.shape_arg(shape), int(nlevels),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return out
+
+
+def mgr_bench_copy(src, dst):
+    """Single-pass copy kernel (achievable-bandwidth calibration)."""
+    _check(src, "src")
+    _check(dst, "dst")
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("dst too small")
+    torch = _torch()
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    _lib.check(_lib.load().mgr_bench_copy(src.data_ptr(), dst.data_ptr(), n, stream))
+    return dst
+
+
+def mgr_finalize():
+    _lib.load().mgr_finalize()
+
+
+def mgr_kernel_name(k):
+    r = _lib.load().mgr_kernel_name(int(k))
+    return None if r is None else r.decode()
+
+
+def kernel_classes():
+    out = {}
+    k = 0
+    while True:
+        n = mgr_kernel_name(k)
+        if n is None:
+            return out
+        out[n] = k
+        k += 1
+
+
+def mgr_timing_enable(kernel, level=-1):
+    if isinstance(kernel, str):
+        kernel = kernel_classes()[kernel]
+    _lib.check(_lib.load().mgr_timing_enable(int(kernel), int(level)))
+
+
+def mgr_timing_disable():
+    _lib.check(_lib.load().mgr_timing_disable())
+
+
+def mgr_timing_read():
+    """(total milliseconds, launch count) of the timed kernel since last read."""
+    import ctypes
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _lib.check(_lib.load().mgr_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def decompose(x, coords=None, nlevels=-1, out=None):
+    """Refactored representation of x (a new tensor unless out is given)."""
+    if out is None:
+        out = _torch().empty_like(x)
+    return mgr_decompose(x, out, coords, nlevels)
+
+
+def recompose(y, coords=None, nlevels=-1, out=None):
+    if out is None:
+        out = _torch().empty_like(y)
+    return mgr_recompose(y, out, coords, nlevels)
+
+
+def decompose_adjoint(g, coords=None, nlevels=-1, out=None):
+    if out is None:
+        out = _torch().empty_like(g)
+    return mgr_decompose_adjoint(g, out, coords, nlevels)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class Decompose(torch.autograd.Function):
+        """y = D x with the hand-written adjoint kernel as backward:
+        dL/dx = D^T dL/dy."""
+
+        @staticmethod
+        def forward(ctx, x, coords=None, nlevels=-1):
+            ctx.coords = coords
+            ctx.nlevels = nlevels
+            return decompose(x.contiguous(), coords, nlevels)
+
+        @staticmethod
+        def backward(ctx, g):
+            return decompose_adjoint(g.contiguous(), ctx.coords, ctx.nlevels), None, None
+
+    return Decompose
+
+
+class _LazyDecompose:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyDecompose._cls is None:
+            _LazyDecompose._cls = _make_autograd()
+        return getattr(_LazyDecompose._cls, name)
+
+
+Decompose = _LazyDecompose()

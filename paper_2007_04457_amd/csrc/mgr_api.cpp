@@ -1,0 +1,806 @@
+// Host side of libmgr: argument validation, FP64 geometry tables, workspace,
+// the level loops of decomposition / recomposition / adjoint, and kernel
+// timing.  Implements include/mgr.h.
+//
+// Level step k (k = 0 finest) acts on the "level grid": the nodes whose
+// indices are all multiples of 2^k, of size m_d = (n_d - 1) / 2^k + 1.  Its
+// coarse nodes (all level indices even) form the next level grid of size
+// (m_d + 1) / 2, which the driver keeps packed in workspace buffers W_{k+1}.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mgr.h"
+#include "mgr_internal.h"
+
+namespace mgr {
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const std::string& msg)
+{
+    g_err = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(MGR_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kMaxDim = 3;
+
+// Per level step: level-grid and coarse sizes and the element offsets of
+// its tables inside the plan's device table buffer (inactive dims unused).
+struct LevelLayout {
+    int64_t m[3], mc[3];
+    size_t w[3], K[3], lf[3], ip[3], up[3];
+};
+
+struct Plan {
+    int device = 0, dtype = 0, ndim = 0, nlevels = 0;
+    int64_t n[3] = {1, 1, 1};
+    int64_t st[3] = {0, 0, 1};
+    bool active[3] = {false, false, false};
+    std::vector<LevelLayout> lv;
+    void* tables = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0, tables_bytes = 0, esize = 4;
+    std::vector<size_t> Woff;  // W_k element offsets, k = 1..L (index k)
+    size_t P1 = 0, P2 = 0, F = 0, Tb = 0;
+};
+
+std::mutex g_mu;
+std::map<std::string, std::unique_ptr<Plan>> g_plans;
+
+// ---- timing ---------------------------------------------------------------
+struct Timing {
+    bool on = false;
+    int kc = -1, level = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+Timing g_tm;
+std::mutex g_tm_mu;
+
+bool capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+template <class Fn>
+hipError_t timed(int kc, int level, hipStream_t st, Fn&& launch)
+{
+    bool want = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        want = g_tm.on && g_tm.kc == kc && (g_tm.level < 0 || g_tm.level == level);
+    }
+    if (!want || capturing(st)) return launch();
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) { (void)hipEventDestroy(a); return e; }
+    (void)hipEventRecord(a, st);
+    e = launch();
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    g_tm.ev.emplace_back(a, b);
+    return e;
+}
+
+// ---- validation -----------------------------------------------------------
+int log2_exact(int64_t v)
+{
+    if (v <= 0) return -1;
+    int k = 0;
+    while (k < 62 && ((int64_t)1 << k) < v) k++;
+    return (((int64_t)1 << k) == v) ? k : -1;
+}
+
+int validate(int dtype, int ndim, const int64_t* shape, const double* const* coords,
+             int* nlevels)
+{
+    if (dtype != MGR_F32 && dtype != MGR_F64) return fail(MGR_ERR_ARG, "dtype must be MGR_F32 or MGR_F64");
+    if (ndim < 1 || ndim > kMaxDim) return fail(MGR_ERR_ARG, "ndim must be 1..3");
+    if (!shape) return fail(MGR_ERR_ARG, "shape is NULL");
+    int kmin = 63;
+    for (int d = 0; d < ndim; d++) {
+        int k = (shape[d] >= 3) ? log2_exact(shape[d] - 1) : -1;
+        if (k < 1)
+            return fail(MGR_ERR_SHAPE, "shape[" + std::to_string(d) + "] = " +
+                                           std::to_string(shape[d]) + " is not 2^k+1 with k >= 1");
+        kmin = std::min(kmin, k);
+    }
+    if (*nlevels == -1) *nlevels = kmin - 1;
+    if (*nlevels < 0 || *nlevels > kmin)
+        return fail(MGR_ERR_LEVELS, "nlevels = " + std::to_string(*nlevels) + " outside 0.." +
+                                        std::to_string(kmin) + " (or -1)");
+    if (coords) {
+        for (int d = 0; d < ndim; d++) {
+            const double* x = coords[d];
+            if (!x) continue;
+            for (int64_t i = 0; i < shape[d]; i++) {
+                if (!std::isfinite(x[i]) || (i > 0 && !(x[i] > x[i - 1])))
+                    return fail(MGR_ERR_COORDS, "coords[" + std::to_string(d) +
+                                                    "] not finite and strictly increasing at " +
+                                                    std::to_string(i));
+            }
+        }
+    }
+    return MGR_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---- FP64 geometry tables (Sec. III-A.2 readings) --------------------------
+// Node positions along a dimension, scaled so the mean finest spacing is 1
+// (only ratios of spacings enter the method).
+std::vector<double> axis_positions(int64_t n, const double* x)
+{
+    std::vector<double> X((size_t)n);
+    if (!x) {
+        for (int64_t i = 0; i < n; i++) X[(size_t)i] = (double)i;
+    } else {
+        double sc = (double)(n - 1) / (x[n - 1] - x[0]);
+        for (int64_t i = 0; i < n; i++) X[(size_t)i] = (x[i] - x[0]) * sc;
+    }
+    return X;
+}
+
+struct DimTab {
+    std::vector<double> w, K, lf, ip, up;
+};
+
+// Tables of one dimension at level step k from the level-grid positions y.
+DimTab build_dim(const std::vector<double>& y)
+{
+    const int64_t m = (int64_t)y.size(), mc = (m + 1) / 2;
+    DimTab t;
+    t.w.assign((size_t)(2 * m), 0.0);
+    for (int64_t j = 1; j < m; j += 2) {
+        double a = (y[j] - y[j - 1]) / (y[j + 1] - y[j - 1]);
+        t.w[(size_t)(2 * j)] = 1.0 - a;
+        t.w[(size_t)(2 * j + 1)] = a;
+    }
+    auto h = [&](int64_t j) { return (j >= 0 && j < m - 1) ? y[j + 1] - y[j] : 0.0; };
+    // Mass matrix entry M(r, c) (piecewise-linear FE mass matrix times 6).
+    auto M = [&](int64_t r, int64_t c) {
+        if (c == r) return 2.0 * (h(r - 1) + h(r));
+        if (c == r - 1) return h(r - 1);
+        if (c == r + 1) return h(r);
+        return 0.0;
+    };
+    // R = P^T: coarse node i collects fine 2i (weight 1), 2i-1 (its upper
+    // interpolation weight) and 2i+1 (its lower interpolation weight).
+    auto PT = [&](int64_t i, int64_t j) {
+        if (j == 2 * i) return 1.0;
+        if (j == 2 * i - 1) return t.w[(size_t)(2 * j + 1)];
+        if (j == 2 * i + 1) return t.w[(size_t)(2 * j)];
+        return 0.0;
+    };
+    t.K.assign((size_t)(5 * mc), 0.0);
+    for (int64_t i = 0; i < mc; i++) {
+        for (int tt = -2; tt <= 2; tt++) {
+            int64_t c = 2 * i + tt;
+            if (c < 0 || c >= m) continue;
+            double s = 0.0;
+            for (int64_t j = 2 * i - 1; j <= 2 * i + 1; j++)
+                if (j >= 0 && j < m) s += PT(i, j) * M(j, c);
+            t.K[(size_t)(5 * i + tt + 2)] = s;
+        }
+    }
+    // Thomas factors of the coarse mass matrix on y[0], y[2], ...
+    t.lf.assign((size_t)mc, 0.0);
+    t.ip.assign((size_t)mc, 0.0);
+    t.up.assign((size_t)mc, 0.0);
+    auto hc = [&](int64_t i) { return (i >= 0 && i < mc - 1) ? y[2 * i + 2] - y[2 * i] : 0.0; };
+    double den_prev = 0.0;
+    for (int64_t i = 0; i < mc; i++) {
+        double diag = 2.0 * (hc(i - 1) + hc(i));
+        double sub = hc(i - 1);
+        double den = diag;
+        if (i > 0) {
+            t.lf[(size_t)i] = sub / den_prev;
+            den = diag - t.lf[(size_t)i] * t.up[(size_t)(i - 1)];
+        }
+        t.up[(size_t)i] = hc(i);
+        t.ip[(size_t)i] = 1.0 / den;
+        den_prev = den;
+    }
+    return t;
+}
+
+std::string plan_key(int device, int dtype, int ndim, const int64_t* shape,
+                     const double* const* coords, int nlevels)
+{
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+    put(&device, sizeof device);
+    put(&dtype, sizeof dtype);
+    put(&ndim, sizeof ndim);
+    put(&nlevels, sizeof nlevels);
+    put(shape, sizeof(int64_t) * (size_t)ndim);
+    for (int d = 0; d < ndim; d++) {
+        const double* x = coords ? coords[d] : nullptr;
+        char flag = x ? 1 : 0;
+        put(&flag, 1);
+        if (x) put(x, sizeof(double) * (size_t)shape[d]);
+    }
+    return k;
+}
+
+size_t workspace_cap()
+{
+    const char* e = std::getenv("MGR_WORKSPACE_MAX");
+    if (!e || !*e) return (size_t)-1;
+    return (size_t)std::strtoull(e, nullptr, 10);
+}
+
+template <typename T>
+void push_table(std::vector<T>& buf, const std::vector<double>& v, size_t* off)
+{
+    *off = buf.size();
+    for (double x : v) buf.push_back((T)x);
+    while (buf.size() % 64) buf.push_back(T(0));
+}
+
+template <typename T>
+int build_plan(Plan& p, const double* const* coords)
+{
+    const int L = p.nlevels;
+    std::vector<std::vector<double>> X(3);
+    for (int d = 0; d < 3; d++)
+        if (p.active[d]) {
+            const int ud = d - (3 - p.ndim);  // user dimension
+            X[d] = axis_positions(p.n[d], coords ? coords[ud] : nullptr);
+        }
+    std::vector<T> host;
+    p.lv.resize((size_t)L);
+    for (int k = 0; k < L; k++) {
+        LevelLayout& ly = p.lv[(size_t)k];
+        for (int d = 0; d < 3; d++) {
+            ly.m[d] = p.active[d] ? ((p.n[d] - 1) >> k) + 1 : 1;
+            ly.mc[d] = p.active[d] ? (ly.m[d] + 1) / 2 : 1;
+            ly.w[d] = ly.K[d] = ly.lf[d] = ly.ip[d] = ly.up[d] = 0;
+            if (!p.active[d]) continue;
+            std::vector<double> y((size_t)ly.m[d]);
+            for (int64_t j = 0; j < ly.m[d]; j++) y[(size_t)j] = X[d][(size_t)(j << k)];
+            DimTab t = build_dim(y);
+            push_table(host, t.w, &ly.w[d]);
+            push_table(host, t.K, &ly.K[d]);
+            push_table(host, t.lf, &ly.lf[d]);
+            push_table(host, t.ip, &ly.ip[d]);
+            push_table(host, t.up, &ly.up[d]);
+        }
+    }
+    // workspace: W_1..W_L, load-vector ping-pong P1/P2, F, adjoint buffer Tb
+    const size_t al = 256 / sizeof(T);
+    size_t off = 0;
+    p.Woff.assign((size_t)L + 1, 0);
+    for (int k = 1; k <= L; k++) {
+        int64_t v = 1;
+        for (int d = 0; d < 3; d++) v *= p.active[d] ? ((p.n[d] - 1) >> k) + 1 : 1;
+        p.Woff[(size_t)k] = off;
+        off = align_up(off + (size_t)v, al);
+    }
+    int64_t sh[3] = {p.n[0], p.n[1], p.n[2]};
+    int64_t V0 = sh[0] * sh[1] * sh[2];
+    std::vector<int64_t> pass_sizes;
+    for (int d = 2; d >= 0; d--) {
+        if (!p.active[d]) continue;
+        sh[d] = (sh[d] + 1) / 2;
+        pass_sizes.push_back(sh[0] * sh[1] * sh[2]);
+    }
+    size_t P1 = pass_sizes.size() >= 2 ? (size_t)pass_sizes[0] : 0;
+    size_t P2 = pass_sizes.size() >= 3 ? (size_t)pass_sizes[1] : 0;
+    size_t Fn = L > 0 ? (size_t)pass_sizes.back() : 0;
+    p.P1 = off; off = align_up(off + P1, al);
+    p.P2 = off; off = align_up(off + P2, al);
+    p.F = off;  off = align_up(off + Fn, al);
+    p.Tb = off; off = align_up(off + (L > 0 ? (size_t)V0 : 0), al);
+    p.esize = sizeof(T);
+    p.ws_bytes = off * sizeof(T);
+    p.tables_bytes = host.size() * sizeof(T);
+    if (p.ws_bytes + p.tables_bytes > workspace_cap())
+        return fail(MGR_ERR_ALLOC, "workspace of " + std::to_string(p.ws_bytes) +
+                                       " bytes exceeds MGR_WORKSPACE_MAX");
+    if (p.tables_bytes) {
+        hipError_t e = hipMalloc(&p.tables, p.tables_bytes);
+        if (e != hipSuccess) return fail(MGR_ERR_ALLOC, std::string("hipMalloc tables: ") + hipGetErrorString(e));
+        e = hipMemcpy(p.tables, host.data(), p.tables_bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload tables");
+    }
+    if (p.ws_bytes) {
+        hipError_t e = hipMalloc(&p.ws, p.ws_bytes);
+        if (e != hipSuccess) {
+            p.ws = nullptr;
+            return fail(MGR_ERR_ALLOC, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+        }
+    }
+    return MGR_OK;
+}
+
+void free_plan(Plan& p)
+{
+    if (p.tables) (void)hipFree(p.tables);
+    if (p.ws) (void)hipFree(p.ws);
+    p.tables = p.ws = nullptr;
+}
+
+int get_plan(int dtype, int ndim, const int64_t* shape, const double* const* coords,
+             int nlevels, hipStream_t st, bool check_capture, Plan** out)
+{
+    int rc = validate(dtype, ndim, shape, coords, &nlevels);
+    if (rc) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::string key = plan_key(dev, dtype, ndim, shape, coords, nlevels);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.get();
+        return MGR_OK;
+    }
+    if (check_capture && capturing(st))
+        return fail(MGR_ERR_CAPTURE, "problem not prepared and the stream is capturing; call mgr_prepare first");
+    auto p = std::make_unique<Plan>();
+    p->device = dev;
+    p->dtype = dtype;
+    p->ndim = ndim;
+    p->nlevels = nlevels;
+    for (int d = 0; d < ndim; d++) {
+        p->n[3 - ndim + d] = shape[d];
+        p->active[3 - ndim + d] = true;
+    }
+    p->st[2] = 1;
+    p->st[1] = p->n[2];
+    p->st[0] = p->n[1] * p->n[2];
+    rc = (dtype == MGR_F32) ? build_plan<float>(*p, coords) : build_plan<double>(*p, coords);
+    if (rc) {
+        free_plan(*p);
+        return rc;
+    }
+    *out = p.get();
+    g_plans.emplace(key, std::move(p));
+    return MGR_OK;
+}
+
+// ---- views ----------------------------------------------------------------
+View3 level_view(const Plan& p, int k)
+{
+    View3 v;
+    for (int d = 0; d < 3; d++) {
+        v.n[d] = p.active[d] ? ((p.n[d] - 1) >> k) + 1 : 1;
+        v.s[d] = p.st[d] << k;
+    }
+    return v;
+}
+
+View3 packed(const int64_t* n)
+{
+    View3 v;
+    for (int d = 0; d < 3; d++) v.n[d] = n[d];
+    v.s[2] = 1;
+    v.s[1] = n[2];
+    v.s[0] = n[1] * n[2];
+    return v;
+}
+
+template <typename T>
+DimTables<T> tables_of(const Plan& p, int k)
+{
+    DimTables<T> tb;
+    const T* base = (const T*)p.tables;
+    const LevelLayout& ly = p.lv[(size_t)k];
+    for (int d = 0; d < 3; d++) {
+        bool a = p.active[d];
+        tb.w[d] = a ? base + ly.w[d] : nullptr;
+        tb.K[d] = a ? base + ly.K[d] : nullptr;
+        tb.lf[d] = a ? base + ly.lf[d] : nullptr;
+        tb.ip[d] = a ? base + ly.ip[d] : nullptr;
+        tb.up[d] = a ? base + ly.up[d] : nullptr;
+    }
+    return tb;
+}
+
+#define MGR_TRY(expr, what)                                \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, what);   \
+    } while (0)
+
+// Load vector f = R M vec(C) of level step k into F (packed coarse shape).
+// Dimensions last to first; the first pass masks the coarse nodes of C.
+template <typename T>
+int load_vector(const Plan& p, int k, const T* C, View3 cv, hipStream_t st)
+{
+    T* ws = (T*)p.ws;
+    DimTables<T> tb = tables_of<T>(p, k);
+    const T* in = C;
+    View3 iv = cv;
+    int64_t sh[3] = {cv.n[0], cv.n[1], cv.n[2]};
+    int npass = 0, done = 0;
+    for (int d = 0; d < 3; d++) npass += p.active[d];
+    for (int d = 2; d >= 0; d--) {
+        if (!p.active[d]) continue;
+        sh[d] = (sh[d] + 1) / 2;
+        T* out = (done == npass - 1) ? ws + p.F : (done == 0 ? ws + p.P1 : ws + p.P2);
+        View3 ov = packed(sh);
+        MGR_TRY(timed(KC_MASSTRANS, k, st,
+                      [&] { return launch_masstrans<T>(in, iv, out, ov, d, tb.K[d], done == 0, st); }),
+                "masstrans launch");
+        in = out;
+        iv = ov;
+        done++;
+    }
+    return MGR_OK;
+}
+
+template <typename T>
+int solve_all(const Plan& p, int k, bool reverse, hipStream_t st)
+{
+    T* ws = (T*)p.ws;
+    DimTables<T> tb = tables_of<T>(p, k);
+    View3 fv = packed(p.lv[(size_t)k].mc);
+    for (int s = 0; s < 3; s++) {
+        int d = reverse ? s : 2 - s;
+        if (!p.active[d]) continue;
+        MGR_TRY(timed(KC_SOLVE, k, st,
+                      [&] { return launch_solve<T>(ws + p.F, fv, d, tb.lf[d], tb.ip[d], tb.up[d], st); }),
+                "solve launch");
+    }
+    return MGR_OK;
+}
+
+View3 full_view(const Plan& p) { return packed(p.n); }
+
+template <typename T>
+int identity_copy(const Plan& p, const void* src, void* dst, hipStream_t st)
+{
+    if (src == dst) return MGR_OK;
+    size_t bytes = (size_t)(p.n[0] * p.n[1] * p.n[2]) * sizeof(T);
+    MGR_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    return MGR_OK;
+}
+
+template <typename T>
+int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
+{
+    const int L = p.nlevels;
+    if (L == 0) return identity_copy<T>(p, src_, dst_, st);
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    T* ws = (T*)p.ws;
+    for (int k = 0; k < L; k++) {
+        const LevelLayout& ly = p.lv[(size_t)k];
+        const T* A = (k == 0) ? src : ws + p.Woff[(size_t)k];
+        View3 av = (k == 0) ? full_view(p) : packed(ly.m);
+        View3 cv = level_view(p, k);
+        T* W = ws + p.Woff[(size_t)k + 1];
+        View3 wv = packed(ly.mc);
+        DimTables<T> tb = tables_of<T>(p, k);
+        MGR_TRY(timed(KC_COEF, k, st, [&] { return launch_coef_decompose<T>(A, av, dst, cv, W, wv, tb, st); }),
+                "coefficient launch");
+        int rc = load_vector<T>(p, k, dst, cv, st);
+        if (rc) return rc;
+        rc = solve_all<T>(p, k, false, st);
+        if (rc) return rc;
+        int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
+        MGR_TRY(timed(KC_APPLY, k, st, [&] { return launch_apply<T>(W, ws + p.F, nc, T(1), st); }),
+                "apply launch");
+    }
+    View3 cl = level_view(p, L);
+    MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                  [&] { return launch_copy_view<T>(ws + p.Woff[(size_t)L], packed(cl.n), dst, cl, st); }),
+            "coarsest scatter");
+    return MGR_OK;
+}
+
+template <typename T>
+int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
+{
+    const int L = p.nlevels;
+    if (L == 0) return identity_copy<T>(p, src_, dst_, st);
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    T* ws = (T*)p.ws;
+    View3 cl = level_view(p, L);
+    MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                  [&] { return launch_copy_view<T>(src, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
+            "coarsest gather");
+    for (int k = L - 1; k >= 0; k--) {
+        const LevelLayout& ly = p.lv[(size_t)k];
+        View3 cv = level_view(p, k);
+        int rc = load_vector<T>(p, k, src, cv, st);
+        if (rc) return rc;
+        rc = solve_all<T>(p, k, false, st);
+        if (rc) return rc;
+        T* W = ws + p.Woff[(size_t)k + 1];
+        int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
+        MGR_TRY(timed(KC_APPLY, k, st, [&] { return launch_apply<T>(W, ws + p.F, nc, T(-1), st); }),
+                "apply launch");
+        T* out = (k == 0) ? dst : ws + p.Woff[(size_t)k];
+        View3 ov = (k == 0) ? full_view(p) : packed(ly.m);
+        DimTables<T> tb = tables_of<T>(p, k);
+        MGR_TRY(timed(KC_INTERP, k, st,
+                      [&] { return launch_interp_recompose<T>(src, cv, out, ov, W, packed(ly.mc), tb, st); }),
+                "interpolation launch");
+    }
+    return MGR_OK;
+}
+
+template <typename T>
+int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
+{
+    const int L = p.nlevels;
+    if (L == 0) return identity_copy<T>(p, src_, dst_, st);
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    T* ws = (T*)p.ws;
+    View3 cl = level_view(p, L);
+    MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                  [&] { return launch_copy_view<T>(src, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
+            "coarsest gather");
+    for (int k = L - 1; k >= 0; k--) {
+        const LevelLayout& ly = p.lv[(size_t)k];
+        T* G = ws + p.Woff[(size_t)k + 1];
+        View3 gv = packed(ly.mc);
+        int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
+        MGR_TRY(hipMemcpyAsync(ws + p.F, G, (size_t)nc * sizeof(T), hipMemcpyDeviceToDevice, st),
+                "adjoint copy");
+        int rc = solve_all<T>(p, k, true, st);
+        if (rc) return rc;
+        DimTables<T> tb = tables_of<T>(p, k);
+        // t = (M P) y, dimensions first to last; the last pass adds g_f.
+        int npass = 0, done = 0;
+        for (int d = 0; d < 3; d++) npass += p.active[d];
+        int64_t sh[3] = {ly.mc[0], ly.mc[1], ly.mc[2]};
+        const T* in = ws + p.F;
+        View3 iv = packed(sh);
+        View3 gf = level_view(p, k);
+        for (int d = 0; d < 3; d++) {
+            if (!p.active[d]) continue;
+            sh[d] = ly.m[d];
+            bool last = (done == npass - 1);
+            T* out = last ? ws + p.Tb : (npass - 2 - done == 0 ? ws + p.P1 : ws + p.P2);
+            View3 ov = packed(sh);
+            MGR_TRY(timed(KC_MASSTRANS_T, k, st,
+                          [&] { return launch_masstrans_t<T>(in, iv, out, ov, d, tb.K[d], src, gf, last, st); }),
+                    "transposed masstrans launch");
+            in = out;
+            iv = ov;
+            done++;
+        }
+        T* out = (k == 0) ? dst : ws + p.Woff[(size_t)k];
+        View3 ov = (k == 0) ? full_view(p) : packed(ly.m);
+        MGR_TRY(timed(KC_ADJ_COMBINE, k, st,
+                      [&] { return launch_adj_combine<T>(ws + p.Tb, packed(ly.m), out, ov, G, gv, tb, st); }),
+                "adjoint combine launch");
+    }
+    return MGR_OK;
+}
+
+enum Direction { DIR_DEC, DIR_REC, DIR_ADJ };
+
+int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+        const double* const* coords, int nlevels, void* stream)
+{
+    g_err.clear();
+    if (!src || !dst) return fail(MGR_ERR_ARG, "src or dst is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    Plan* p = nullptr;
+    int rc = get_plan(dtype, ndim, shape, coords, nlevels, st, true, &p);
+    if (rc) return rc;
+    if (dtype == MGR_F32) {
+        switch (dir) {
+            case DIR_DEC: return run_decompose<float>(*p, src, dst, st);
+            case DIR_REC: return run_recompose<float>(*p, src, dst, st);
+            default: return run_adjoint<float>(*p, src, dst, st);
+        }
+    }
+    switch (dir) {
+        case DIR_DEC: return run_decompose<double>(*p, src, dst, st);
+        case DIR_REC: return run_recompose<double>(*p, src, dst, st);
+        default: return run_adjoint<double>(*p, src, dst, st);
+    }
+}
+
+const char* const kKernelNames[KC_COUNT] = {
+    "coef_decompose", "masstrans", "solve", "apply", "interp_recompose",
+    "masstrans_t", "adj_combine", "copy_view", "bench_copy"};
+
+}  // namespace
+}  // namespace mgr
+
+using namespace mgr;
+
+extern "C" {
+
+int mgr_max_levels(int ndim, const int64_t* shape)
+{
+    int nl = -1;
+    int rc = validate(MGR_F32, ndim, shape, nullptr, &nl);
+    return rc ? -rc : nl;
+}
+
+int mgr_decompose(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                  const double* const* coords, int nlevels, void* stream)
+{
+    try {
+        return run(DIR_DEC, src, dst, dtype, ndim, shape, coords, nlevels, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_recompose(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                  const double* const* coords, int nlevels, void* stream)
+{
+    try {
+        return run(DIR_REC, src, dst, dtype, ndim, shape, coords, nlevels, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_decompose_adjoint(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                          const double* const* coords, int nlevels, void* stream)
+{
+    try {
+        return run(DIR_ADJ, src, dst, dtype, ndim, shape, coords, nlevels, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_prepare(int dtype, int ndim, const int64_t* shape, const double* const* coords,
+                int nlevels)
+{
+    try {
+        g_err.clear();
+        Plan* p = nullptr;
+        return get_plan(dtype, ndim, shape, coords, nlevels, nullptr, false, &p);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_class_map(int ndim, const int64_t* shape, int nlevels, uint8_t* out)
+{
+    g_err.clear();
+    if (!out) return fail(MGR_ERR_ARG, "out is NULL");
+    int rc = validate(MGR_F32, ndim, shape, nullptr, &nlevels);
+    if (rc) return rc;
+    int64_t n[3] = {1, 1, 1};
+    for (int d = 0; d < ndim; d++) n[3 - ndim + d] = shape[d];
+    const int L = nlevels;
+    auto v2 = [L](int64_t i) {
+        if (i == 0) return L;
+        int v = 0;
+        while (((i >> v) & 1) == 0 && v < L) v++;
+        return v;
+    };
+    size_t idx = 0;
+    for (int64_t a = 0; a < n[0]; a++)
+        for (int64_t b = 0; b < n[1]; b++) {
+            int vab = std::min(v2(a), v2(b));
+            for (int64_t c = 0; c < n[2]; c++) {
+                int v = std::min(vab, v2(c));
+                out[idx++] = (uint8_t)(v >= L ? 0 : L - v);
+            }
+        }
+    return MGR_OK;
+}
+
+const char* mgr_status_string(int status)
+{
+    switch (status) {
+        case MGR_OK: return "ok";
+        case MGR_ERR_ARG: return "invalid argument";
+        case MGR_ERR_SHAPE: return "invalid shape (sizes must be 2^k+1, k>=1)";
+        case MGR_ERR_LEVELS: return "invalid level count";
+        case MGR_ERR_COORDS: return "invalid coordinates";
+        case MGR_ERR_HIP: return "HIP runtime error";
+        case MGR_ERR_ALLOC: return "allocation failed";
+        case MGR_ERR_CAPTURE: return "allocation needed during stream capture";
+        default: return "unknown status";
+    }
+}
+
+const char* mgr_last_error(void) { return g_err.c_str(); }
+
+void mgr_finalize(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : g_plans) free_plan(*kv.second);
+    g_plans.clear();
+    std::lock_guard<std::mutex> lk2(g_tm_mu);
+    for (auto& e : g_tm.ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    g_tm.ev.clear();
+    g_tm.on = false;
+}
+
+int mgr_bench_copy(const void* src, void* dst, size_t nbytes, void* stream)
+{
+    g_err.clear();
+    if (!src || !dst) return fail(MGR_ERR_ARG, "src or dst is NULL");
+    if (nbytes % 16 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+        return fail(MGR_ERR_ARG, "nbytes and pointers must be multiples of 16");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = timed(KC_BENCH_COPY, 0, st, [&] { return launch_bench_copy(src, dst, nbytes, st); });
+    return e == hipSuccess ? MGR_OK : hip_fail(e, "copy launch");
+}
+
+int mgr_timing_enable(int kernel, int level)
+{
+    if (kernel < 0 || kernel >= KC_COUNT) return fail(MGR_ERR_ARG, "unknown kernel class");
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    g_tm.on = true;
+    g_tm.kc = kernel;
+    g_tm.level = level;
+    return MGR_OK;
+}
+
+int mgr_timing_disable(void)
+{
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    g_tm.on = false;
+    return MGR_OK;
+}
+
+int mgr_timing_read(double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return fail(MGR_ERR_ARG, "NULL output");
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_tm_mu);
+        ev.swap(g_tm.ev);
+    }
+    double sum = 0.0;
+    int rc = MGR_OK;
+    for (auto& e : ev) {
+        float ms = 0.f;
+        hipError_t r = hipEventSynchronize(e.second);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e.first, e.second);
+        if (r != hipSuccess && rc == MGR_OK) rc = hip_fail(r, "timing events");
+        sum += ms;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    *total_ms = sum;
+    *launches = (int64_t)ev.size();
+    return rc;
+}
+
+const char* mgr_kernel_name(int kernel)
+{
+    if (kernel < 0 || kernel >= KC_COUNT) return nullptr;
+    return kKernelNames[kernel];
+}
+
+}  // extern "C"

@@ -1,0 +1,403 @@
+// gfx950 kernels of the multigrid refactoring path (arXiv 2007.04457,
+// Sec. II-A and III-A).  All kernels are memory bound; none is a dense
+// contraction, so nothing here uses MFMA.
+//
+// Every kernel works on strided 3-D views (mgr::View3) of either the caller's
+// array at the stride 2^k of level step k, or packed workspace arrays.
+#include "mgr_internal.h"
+
+namespace mgr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void decode3(int64_t idx, const int64_t* n, int64_t* j)
+{
+    j[2] = idx % n[2];
+    int64_t t = idx / n[2];
+    j[1] = t % n[1];
+    j[0] = t / n[1];
+}
+
+__device__ __forceinline__ int64_t at(const View3& v, int64_t j0, int64_t j1, int64_t j2)
+{
+    return j0 * v.s[0] + j1 * v.s[1] + j2 * v.s[2];
+}
+
+inline unsigned grid_for(int64_t total)
+{
+    int64_t b = (total + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > (int64_t)1 << 22) b = (int64_t)1 << 22;  // grid-stride beyond this
+    return (unsigned)b;
+}
+
+// Interpolation corners of level-grid node j: per dimension the lower and
+// upper coarse neighbour and their weights (an even index is its own corner
+// with weight 1 and a zero-weight upper duplicate).
+template <typename T>
+struct Corners {
+    int64_t lo[3], hi[3];
+    T wl[3], wh[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void corners(const int64_t* j, const DimTables<T>& tb, Corners<T>& c)
+{
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        if (j[d] & 1) {
+            c.lo[d] = j[d] - 1;
+            c.hi[d] = j[d] + 1;
+            c.wl[d] = tb.w[d][2 * j[d]];
+            c.wh[d] = tb.w[d][2 * j[d] + 1];
+        } else {
+            c.lo[d] = j[d];
+            c.hi[d] = j[d];
+            c.wl[d] = T(1);
+            c.wh[d] = T(0);
+        }
+    }
+}
+
+// Multilinear interpolation from the coarse corners, evaluated separably
+// (along dim 2, then 1, then 0).  `half` maps level-grid corner indices to
+// a packed coarse array (index / 2) when set.
+template <typename T, bool kHalf>
+__device__ __forceinline__ T interp_corners(const T* __restrict__ A, const View3& av,
+                                            const Corners<T>& c)
+{
+    T r0[2];
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+        int64_t i0 = a ? c.hi[0] : c.lo[0];
+        T r1[2];
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            int64_t i1 = b ? c.hi[1] : c.lo[1];
+            int64_t l2 = c.lo[2], h2 = c.hi[2];
+            int64_t q0 = kHalf ? i0 >> 1 : i0, q1 = kHalf ? i1 >> 1 : i1;
+            T vlo = A[at(av, q0, q1, kHalf ? l2 >> 1 : l2)];
+            T vhi = (h2 != l2) ? A[at(av, q0, q1, kHalf ? h2 >> 1 : h2)] : T(0);
+            r1[b] = c.wl[2] * vlo + c.wh[2] * vhi;
+            if (c.hi[1] == c.lo[1]) { r1[1] = T(0); break; }
+        }
+        r0[a] = c.wl[1] * r1[0] + c.wh[1] * r1[1];
+        if (c.hi[0] == c.lo[0]) { r0[1] = T(0); break; }
+    }
+    return c.wl[0] * r0[0] + c.wh[0] * r0[1];
+}
+
+// Coefficients (Sec. II-A.1) of one level step: c(p) = u(p) - Pi u(p) at
+// fine-only nodes, written to C; coarse values copied packed to W.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_coef_decompose(const T* A, View3 av, T* C, View3 cv,  // A and C may alias (in place)
+                 T* __restrict__ W, View3 wv, DimTables<T> tb, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t j[3];
+        decode3(idx, av.n, j);
+        T u = A[at(av, j[0], j[1], j[2])];
+        if (((j[0] | j[1] | j[2]) & 1) == 0) {
+            W[at(wv, j[0] >> 1, j[1] >> 1, j[2] >> 1)] = u;
+            continue;
+        }
+        Corners<T> c;
+        corners(j, tb, c);
+        C[at(cv, j[0], j[1], j[2])] = u - interp_corners<T, false>(A, av, c);
+    }
+}
+
+// One dimension of the load vector f = R M vec(C) (Sec. III-A.2, merged
+// "mass-trans" stencil): Y(.., i, ..) = sum_t K_i[t] X(.., 2i+t, ..).  With
+// mask_coarse, X values at nodes whose indices are all even read as zero
+// (C is zero on N_{l-1}).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_masstrans(const T* __restrict__ X, View3 xv, T* __restrict__ Y, View3 yv, int d,
+            const T* __restrict__ K, int mask_coarse, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t o[3];
+        decode3(idx, yv.n, o);
+        const int64_t i = o[d], m_in = xv.n[d];
+        int64_t j[3] = {o[0], o[1], o[2]};
+        int64_t oth = 0;
+#pragma unroll
+        for (int e = 0; e < 3; e++)
+            if (e != d) oth |= o[e];
+        const bool others_even = (oth & 1) == 0;
+        T s = T(0);
+#pragma unroll
+        for (int t = -2; t <= 2; t++) {
+            int64_t jd = 2 * i + t;
+            if (jd < 0 || jd >= m_in) continue;
+            j[d] = jd;
+            T v = X[at(xv, j[0], j[1], j[2])];
+            if (mask_coarse && others_even && ((jd & 1) == 0)) v = T(0);
+            s += K[5 * i + t + 2] * v;
+        }
+        Y[at(yv, o[0], o[1], o[2])] = s;
+    }
+}
+
+// Correction solve (Sec. II-A.2, Sec. III-A.3): one Thomas solve of the
+// coarse mass matrix per fibre along d, in place.  One thread per fibre.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_solve(T* __restrict__ F, View3 fv, int d, const T* __restrict__ lf,
+        const T* __restrict__ ip, const T* __restrict__ up, int64_t nfib)
+{
+    const int da = (d == 0) ? 1 : 0;
+    const int db = (d == 2) ? 1 : 2;
+    const int64_t n = fv.n[d], sd = fv.s[d];
+    for (int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x; f < nfib;
+         f += (int64_t)gridDim.x * kBlock) {
+        const int64_t ja = f / fv.n[db], jb = f % fv.n[db];
+        T* p = F + ja * fv.s[da] + jb * fv.s[db];
+        T g = p[0];
+        for (int64_t i = 1; i < n; i++) {
+            g = p[i * sd] - lf[i] * g;
+            p[i * sd] = g;
+        }
+        T z = g * ip[n - 1];
+        p[(n - 1) * sd] = z;
+        for (int64_t i = n - 2; i >= 0; i--) {
+            z = (p[i * sd] - up[i] * z) * ip[i];
+            p[i * sd] = z;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_apply(T* __restrict__ W, const T* __restrict__ F, int64_t n, T sign)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        W[i] += sign * F[i];
+}
+
+// Recomposition of one level step: coarse nodes take the corrected coarse
+// values W, fine-only nodes c(p) + Pi u(p).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_interp_recompose(const T* C, View3 cv, T* Out, View3 ov,  // C and Out may alias
+                   const T* __restrict__ W, View3 wv, DimTables<T> tb, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t j[3];
+        decode3(idx, cv.n, j);
+        T r;
+        if (((j[0] | j[1] | j[2]) & 1) == 0) {
+            r = W[at(wv, j[0] >> 1, j[1] >> 1, j[2] >> 1)];
+        } else {
+            Corners<T> c;
+            corners(j, tb, c);
+            r = C[at(cv, j[0], j[1], j[2])] + interp_corners<T, true>(W, wv, c);
+        }
+        Out[at(ov, j[0], j[1], j[2])] = r;
+    }
+}
+
+// Transposed load-vector stencil along d: X(.., j, ..) = sum_i K_i[j-2i] Y(.., i, ..)
+// (the operator M P of the adjoint).  With use_add the addend is added at
+// fine-only nodes of the output grid.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_masstrans_t(const T* __restrict__ Y, View3 yv, T* __restrict__ X, View3 xv, int d,
+              const T* __restrict__ K, const T* __restrict__ add, View3 addv, int use_add,
+              int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t j[3];
+        decode3(idx, xv.n, j);
+        const int64_t jd = j[d], mc = yv.n[d];
+        int64_t q[3] = {j[0], j[1], j[2]};
+        T s = T(0);
+        const int64_t i0 = (jd >> 1) - 1;
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            int64_t i = i0 + r;
+            int64_t t = jd - 2 * i;
+            if (i < 0 || i >= mc || t < -2 || t > 2) continue;
+            q[d] = i;
+            s += K[5 * i + t + 2] * Y[at(yv, q[0], q[1], q[2])];
+        }
+        if (use_add && ((j[0] | j[1] | j[2]) & 1)) s += add[at(addv, j[0], j[1], j[2])];
+        X[at(xv, j[0], j[1], j[2])] = s;
+    }
+}
+
+// Last stage of the adjoint level step: fine-only nodes take Tb (already
+// g_f + M P y), coarse nodes G - Pi^T Tb (gather of the transposed
+// interpolation from the up to 26 fine neighbours).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_combine(const T* __restrict__ Tb, View3 tv, T* __restrict__ Out, View3 ov,
+              const T* __restrict__ G, View3 gv, DimTables<T> tb, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t j[3];
+        decode3(idx, tv.n, j);
+        if ((j[0] | j[1] | j[2]) & 1) {
+            Out[at(ov, j[0], j[1], j[2])] = Tb[at(tv, j[0], j[1], j[2])];
+            continue;
+        }
+        T s = T(0);
+        for (int a = -1; a <= 1; a++) {
+            int64_t p0 = j[0] + a;
+            if (p0 < 0 || p0 >= tv.n[0]) continue;
+            T w0 = (a == 0) ? T(1) : (a > 0 ? tb.w[0][2 * p0] : tb.w[0][2 * p0 + 1]);
+            for (int b = -1; b <= 1; b++) {
+                int64_t p1 = j[1] + b;
+                if (p1 < 0 || p1 >= tv.n[1]) continue;
+                T w1 = (b == 0) ? T(1) : (b > 0 ? tb.w[1][2 * p1] : tb.w[1][2 * p1 + 1]);
+                for (int c = -1; c <= 1; c++) {
+                    int64_t p2 = j[2] + c;
+                    if (p2 < 0 || p2 >= tv.n[2]) continue;
+                    if (a == 0 && b == 0 && c == 0) continue;
+                    T w2 = (c == 0) ? T(1) : (c > 0 ? tb.w[2][2 * p2] : tb.w[2][2 * p2 + 1]);
+                    s += w0 * w1 * w2 * Tb[at(tv, p0, p1, p2)];
+                }
+            }
+        }
+        Out[at(ov, j[0], j[1], j[2])] = G[at(gv, j[0] >> 1, j[1] >> 1, j[2] >> 1)] - s;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_copy_view(const T* __restrict__ X, View3 xv, T* __restrict__ Y, View3 yv, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t j[3];
+        decode3(idx, yv.n, j);
+        Y[at(yv, j[0], j[1], j[2])] = X[at(xv, j[0], j[1], j[2])];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bench_copy(const uint4* __restrict__ s, uint4* __restrict__ d, int64_t n16)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * kBlock)
+        d[i] = s[i];
+}
+
+inline int64_t vol(const View3& v) { return v.n[0] * v.n[1] * v.n[2]; }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_coef_decompose(const T* A, View3 av, T* C, View3 cv, T* W, View3 wv,
+                                 DimTables<T> tb, hipStream_t st)
+{
+    int64_t total = vol(av);
+    hipLaunchKernelGGL(k_coef_decompose<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, A, av,
+                       C, cv, W, wv, tb, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_masstrans(const T* X, View3 xv, T* Y, View3 yv, int d, const T* K,
+                            int mask_coarse, hipStream_t st)
+{
+    int64_t total = vol(yv);
+    hipLaunchKernelGGL(k_masstrans<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, X, xv, Y,
+                       yv, d, K, mask_coarse, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_solve(T* F, View3 fv, int d, const T* lf, const T* ip, const T* up,
+                        hipStream_t st)
+{
+    int64_t nfib = vol(fv) / fv.n[d];
+    hipLaunchKernelGGL(k_solve<T>, dim3(grid_for(nfib)), dim3(kBlock), 0, st, F, fv, d, lf, ip,
+                       up, nfib);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply(T* W, const T* F, int64_t n, T sign, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_apply<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, W, F, n, sign);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp_recompose(const T* C, View3 cv, T* Out, View3 ov, const T* W,
+                                   View3 wv, DimTables<T> tb, hipStream_t st)
+{
+    int64_t total = vol(cv);
+    hipLaunchKernelGGL(k_interp_recompose<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, C,
+                       cv, Out, ov, W, wv, tb, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_masstrans_t(const T* Y, View3 yv, T* X, View3 xv, int d, const T* K,
+                              const T* add, View3 addv, int use_add, hipStream_t st)
+{
+    int64_t total = vol(xv);
+    hipLaunchKernelGGL(k_masstrans_t<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, Y, yv, X,
+                       xv, d, K, add, addv, use_add, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_combine(const T* Tb, View3 tv, T* Out, View3 ov, const T* G,
+                              View3 gv, DimTables<T> tb, hipStream_t st)
+{
+    int64_t total = vol(tv);
+    hipLaunchKernelGGL(k_adj_combine<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, Tb, tv,
+                       Out, ov, G, gv, tb, total);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_view(const T* X, View3 xv, T* Y, View3 yv, hipStream_t st)
+{
+    int64_t total = vol(yv);
+    hipLaunchKernelGGL(k_copy_view<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, X, xv, Y,
+                       yv, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStream_t st)
+{
+    int64_t n16 = (int64_t)(nbytes / 16);
+    hipLaunchKernelGGL(k_bench_copy, dim3(grid_for(n16)), dim3(kBlock), 0, st,
+                       (const uint4*)src, (uint4*)dst, n16);
+    return hipGetLastError();
+}
+
+#define MGR_INSTANTIATE(T)                                                                      \
+    template hipError_t launch_coef_decompose<T>(const T*, View3, T*, View3, T*, View3,         \
+                                                 DimTables<T>, hipStream_t);                    \
+    template hipError_t launch_masstrans<T>(const T*, View3, T*, View3, int, const T*, int,     \
+                                            hipStream_t);                                       \
+    template hipError_t launch_solve<T>(T*, View3, int, const T*, const T*, const T*,           \
+                                        hipStream_t);                                           \
+    template hipError_t launch_apply<T>(T*, const T*, int64_t, T, hipStream_t);                 \
+    template hipError_t launch_interp_recompose<T>(const T*, View3, T*, View3, const T*, View3, \
+                                                   DimTables<T>, hipStream_t);                  \
+    template hipError_t launch_masstrans_t<T>(const T*, View3, T*, View3, int, const T*,        \
+                                              const T*, View3, int, hipStream_t);               \
+    template hipError_t launch_adj_combine<T>(const T*, View3, T*, View3, const T*, View3,      \
+                                              DimTables<T>, hipStream_t);                       \
+    template hipError_t launch_copy_view<T>(const T*, View3, T*, View3, hipStream_t);
+
+MGR_INSTANTIATE(float)
+MGR_INSTANTIATE(double)
+
+}  // namespace mgr
