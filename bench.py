@@ -1,0 +1,213 @@
+"""Benchmark: decomposition + recomposition throughput at 513^3 on one GPU.
+
+One step = decompose + recompose of a 513x513x513 field (full decomposition,
+8 level steps) with the library's HIP path; inputs are resident in HBM before
+the timed region.  Throughput = input bytes per direction / time, the
+refactoring throughput the paper reports (Sec. IV-C), so one step counts
+2 * N * sizeof(dtype) bytes.
+
+Prints one JSON line.  Besides the headline (float32, sinusoid-plus-noise
+field) it reports float64, the Gaussian-blob field, separate decompose and
+recompose times, the single-pass copy bandwidth, the roofline of the
+dominant kernel (HIP events around its launches in the timed region) and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+SHAPE = (513, 513, 513)
+SEED_SIN, SEED_BLOB = 1, 2
+
+# Dominant kernel and its algorithmic bytes per level-0 launch.  The streaming
+# decomposition kernel reads the level grid once (V nodes) and writes every
+# node once (coefficients at fine-only nodes, u at coarse positions so rows
+# are written whole), the packed coarse values (Vc) and the load vector (Vc).
+DOMINANT = "stream_dec"
+
+
+def algorithmic_bytes(kernel, shape, s):
+    V = int(np.prod(shape))
+    Vc = int(np.prod([(n + 1) // 2 for n in shape]))
+    if kernel == "stream_dec":
+        return (2 * V + 2 * Vc) * s
+    if kernel == "stream_load":
+        return (V + Vc) * s
+    if kernel == "interp_recompose":
+        return (V + Vc + V) * s  # coefficients + coarse values in, V out
+    raise ValueError(kernel)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="headline only (float32 sinusoid)")
+    return ap.parse_args()
+
+
+def timed_steps(mgr, torch, x, y, r, steps, warmup, on_start=None):
+    for _ in range(warmup):
+        mgr.mgr_decompose(x, y)
+        mgr.mgr_recompose(y, r)
+    torch.cuda.synchronize()
+    if on_start:
+        on_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mgr.mgr_decompose(x, y)
+        mgr.mgr_recompose(y, r)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def split_times(mgr, torch, x, y, r, reps=5):
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    td, tr = [], []
+    for _ in range(reps):
+        e[0].record()
+        mgr.mgr_decompose(x, y)
+        e[1].record()
+        mgr.mgr_recompose(y, r)
+        e[2].record()
+        torch.cuda.synchronize()
+        td.append(e[0].elapsed_time(e[1]))
+        tr.append(e[1].elapsed_time(e[2]))
+    return float(np.median(td)), float(np.median(tr))
+
+
+def copy_bandwidth(mgr, torch, nbytes=1 << 30, reps=10):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        mgr.mgr_bench_copy(a, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mgr.mgr_bench_copy(a, b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    return 2.0 * nbytes / dt / 1e9  # read + write bytes per second
+
+
+def cpu_baseline():
+    """The CPU oracle (FP64, single thread) on a bounded sample: one 257^3
+    sinusoid-plus-noise field and one 257^3 blob field, each decomposed and
+    recomposed once; reported as the float32 workload's GB/s (4 bytes/node)."""
+    import oracle
+    from paper_2007_04457_amd import synth
+
+    shape = (257, 257, 257)
+    n = int(np.prod(shape))
+    t = 0.0
+    for gen, seed in ((synth.sinusoid_field, SEED_SIN), (synth.blob_field, SEED_BLOB)):
+        u, _ = gen(shape, seed)
+        u = u.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        d = oracle.decompose(u)
+        oracle.recompose(d)
+        t += time.perf_counter() - t0
+    gbps = 2 * 2 * n * 4 / t / 1e9
+    return {"value": round(gbps, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "257^3 sinusoid + 257^3 blob fields, FP64 oracle, one decompose+recompose each, "
+                      f"{t:.1f} s; rate counted in float32 input bytes (4 B/node) per direction"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2007_04457_amd as mgr
+    from paper_2007_04457_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    N = int(np.prod(SHAPE))
+    L = mgr.mgr_max_levels(SHAPE)
+
+    print(f"[bench] generating 513^3 fields", file=sys.stderr, flush=True)
+    u_sin, _ = synth.sinusoid_field(SHAPE, SEED_SIN)
+    u_blob = None if args.quick else synth.blob_field(SHAPE, SEED_BLOB)[0]
+
+    results = {}
+    roof = None
+    for dt_name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        if args.quick and dt_name == "f64":
+            continue
+        s = 4 if dt == torch.float32 else 8
+        for fname, u in (("sinusoid", u_sin), ("blobs", u_blob)):
+            if u is None:
+                continue
+            x = torch.from_numpy(u).to(dt).to(dev)
+            y = torch.empty_like(x)
+            r = torch.empty_like(x)
+            mgr.mgr_prepare(dt, SHAPE)
+            headline = (dt_name == "f32" and fname == "sinusoid")
+            print(f"[bench] {dt_name} {fname}: {args.warmup} warmup + {args.steps} steps",
+                  file=sys.stderr, flush=True)
+            def start_timing():
+                mgr.mgr_timing_read()  # clear
+                mgr.mgr_timing_enable(DOMINANT, 0)
+            sec = timed_steps(mgr, torch, x, y, r, args.steps, args.warmup,
+                              start_timing if headline else None)
+            if headline:
+                ms_tot, launches = mgr.mgr_timing_read()
+                mgr.mgr_timing_disable()
+                if launches == 0:
+                    raise RuntimeError(f"kernel {DOMINANT} was not launched at level 0")
+                per_launch_ms = ms_tot / launches
+                ab = algorithmic_bytes(DOMINANT, SHAPE, s)
+                achieved = ab / (per_launch_ms * 1e-3) / 1e9
+                roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                        "kernel": DOMINANT, "level": 0, "launch_ms": round(per_launch_ms, 4),
+                        "launches": launches, "algorithmic_bytes": ab}
+            td, tr = split_times(mgr, torch, x, y, r)
+            torch.cuda.synchronize()
+            err = float((r - x).abs().max().item() / x.abs().max().item())
+            results[(dt_name, fname)] = {
+                "GBps": round(2 * N * s / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 4),
+                "t_decompose_ms": round(td, 4), "t_recompose_ms": round(tr, 4),
+                "roundtrip_max_rel_err": err}
+            del x, y, r
+            torch.cuda.empty_cache()
+
+    head = results[("f32", "sinusoid")]
+    copy_gbps = copy_bandwidth(mgr, torch)
+    out = {
+        "metric": "decompose+recompose GB/s at 513^3 fp32/fp64; % HBM peak; batched vs serial",
+        "value": head["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "513^3 uniform grid, sinusoid-plus-noise field (seed 1), "
+                               f"full decomposition ({L} level steps) then recomposition",
+                   "shape": list(SHAPE), "nlevels": L},
+        "roofline": roof,
+        "t_decompose_ms": head["t_decompose_ms"], "t_recompose_ms": head["t_recompose_ms"],
+        "roundtrip_max_rel_err": head["roundtrip_max_rel_err"],
+        "copy_kernel_GBps": round(copy_gbps, 1),
+        "variants": {f"{k[0]}_{k[1]}": v for k, v in results.items()},
+    }
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -44,7 +44,9 @@ constexpr int kMaxDim = 3;
 // its tables inside the plan's device table buffer (inactive dims unused).
 struct LevelLayout {
     int64_t m[3], mc[3];
-    size_t w[3], K[3], lf[3], ip[3], up[3];
+    size_t w[3], K[3];
+    size_t sub[3], sup[3], lseg[3], ipseg[3], alpha[3], beta[3], sl[3], sip[3], su[3];
+    int S[3];
 };
 
 struct Plan {
@@ -52,12 +54,13 @@ struct Plan {
     int64_t n[3] = {1, 1, 1};
     int64_t st[3] = {0, 0, 1};
     bool active[3] = {false, false, false};
+    int udim[3] = {-1, -1, -1};  // user dimension of each internal dimension
     std::vector<LevelLayout> lv;
     void* tables = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0, tables_bytes = 0, esize = 4;
     std::vector<size_t> Woff;  // W_k element offsets, k = 1..L (index k)
-    size_t P1 = 0, P2 = 0, F = 0, Tb = 0;
+    size_t P1 = 0, P2 = 0, F = 0, Tb = 0, Yb = 0;
 };
 
 std::mutex g_mu;
@@ -161,7 +164,7 @@ std::vector<double> axis_positions(int64_t n, const double* x)
 }
 
 struct DimTab {
-    std::vector<double> w, K, lf, ip, up;
+    std::vector<double> w, K;
 };
 
 // Tables of one dimension at level step k from the level-grid positions y.
@@ -202,23 +205,87 @@ DimTab build_dim(const std::vector<double>& y)
             t.K[(size_t)(5 * i + tt + 2)] = s;
         }
     }
-    // Thomas factors of the coarse mass matrix on y[0], y[2], ...
-    t.lf.assign((size_t)mc, 0.0);
-    t.ip.assign((size_t)mc, 0.0);
-    t.up.assign((size_t)mc, 0.0);
-    auto hc = [&](int64_t i) { return (i >= 0 && i < mc - 1) ? y[2 * i + 2] - y[2 * i] : 0.0; };
-    double den_prev = 0.0;
-    for (int64_t i = 0; i < mc; i++) {
-        double diag = 2.0 * (hc(i - 1) + hc(i));
-        double sub = hc(i - 1);
-        double den = diag;
-        if (i > 0) {
-            t.lf[(size_t)i] = sub / den_prev;
-            den = diag - t.lf[(size_t)i] * t.up[(size_t)(i - 1)];
+    return t;
+}
+
+struct SolveTab {
+    std::vector<double> sub, sup, lseg, ipseg, alpha, beta, sl, sip, su;
+    int S = 1;
+};
+
+// Partitioned-Thomas tables of the coarse mass matrix on positions yc
+// (segment length kSeg; see mgr_solve.hip for the scheme).
+SolveTab build_solve(const std::vector<double>& yc)
+{
+    const int64_t n = (int64_t)yc.size();
+    SolveTab t;
+    auto hc = [&](int64_t i) { return (i >= 0 && i < n - 1) ? yc[(size_t)(i + 1)] - yc[(size_t)i] : 0.0; };
+    std::vector<double> diag((size_t)n);
+    t.sub.assign((size_t)n, 0.0);
+    t.sup.assign((size_t)n, 0.0);
+    for (int64_t i = 0; i < n; i++) {
+        t.sub[(size_t)i] = hc(i - 1);
+        t.sup[(size_t)i] = hc(i);
+        diag[(size_t)i] = 2.0 * (hc(i - 1) + hc(i));
+    }
+    // n - 1 is a power of two, so it is a multiple of kSeg once >= kSeg
+    t.S = (n - 1 >= kSeg) ? (int)((n - 1) / kSeg) : 1;
+    const int S = t.S;
+    t.lseg.assign((size_t)n, 0.0);
+    t.ipseg.assign((size_t)n, 0.0);
+    t.alpha.assign((size_t)n, 0.0);
+    t.beta.assign((size_t)n, 0.0);
+    for (int s = 0; s < S; s++) {
+        const int64_t lo = (int64_t)s * kSeg + (s > 0 ? 1 : 0);
+        const int64_t hi = (s == S - 1) ? n : (int64_t)(s + 1) * kSeg;
+        double den = 0.0;
+        for (int64_t i = lo; i < hi; i++) {
+            if (i == lo) {
+                den = diag[(size_t)i];
+            } else {
+                t.lseg[(size_t)i] = t.sub[(size_t)i] / den;
+                den = diag[(size_t)i] - t.lseg[(size_t)i] * t.sup[(size_t)(i - 1)];
+            }
+            t.ipseg[(size_t)i] = 1.0 / den;
         }
-        t.up[(size_t)i] = hc(i);
-        t.ip[(size_t)i] = 1.0 / den;
-        den_prev = den;
+        auto local_solve = [&](std::vector<double>& v) {
+            for (int64_t i = lo + 1; i < hi; i++) v[(size_t)i] -= t.lseg[(size_t)i] * v[(size_t)(i - 1)];
+            for (int64_t i = hi - 1; i >= lo; i--) {
+                double z = (i == hi - 1) ? 0.0 : v[(size_t)(i + 1)];
+                v[(size_t)i] = (v[(size_t)i] - t.sup[(size_t)i] * z) * t.ipseg[(size_t)i];
+            }
+        };
+        if (s > 0) {
+            std::vector<double> v((size_t)n, 0.0);
+            v[(size_t)lo] = -t.sub[(size_t)lo];
+            local_solve(v);
+            for (int64_t i = lo; i < hi; i++) t.alpha[(size_t)i] = v[(size_t)i];
+        }
+        if (s < S - 1) {
+            std::vector<double> v((size_t)n, 0.0);
+            v[(size_t)(hi - 1)] = -t.sup[(size_t)(hi - 1)];
+            local_solve(v);
+            for (int64_t i = lo; i < hi; i++) t.beta[(size_t)i] = v[(size_t)i];
+        }
+    }
+    t.sl.assign((size_t)S, 0.0);
+    t.sip.assign((size_t)S, 0.0);
+    t.su.assign((size_t)S, 0.0);
+    double den = 0.0;
+    for (int s = 1; s < S; s++) {
+        const int64_t p = (int64_t)s * kSeg;
+        const double L = t.sub[(size_t)p] * t.alpha[(size_t)(p - 1)];
+        const double D = diag[(size_t)p] + t.sub[(size_t)p] * t.beta[(size_t)(p - 1)] +
+                         t.sup[(size_t)p] * t.alpha[(size_t)(p + 1)];
+        const double U = t.sup[(size_t)p] * t.beta[(size_t)(p + 1)];
+        if (s == 1) {
+            den = D;
+        } else {
+            t.sl[(size_t)s] = L / den;
+            den = D - t.sl[(size_t)s] * t.su[(size_t)(s - 1)];
+        }
+        t.su[(size_t)s] = U;
+        t.sip[(size_t)s] = 1.0 / den;
     }
     return t;
 }
@@ -263,10 +330,7 @@ int build_plan(Plan& p, const double* const* coords)
     const int L = p.nlevels;
     std::vector<std::vector<double>> X(3);
     for (int d = 0; d < 3; d++)
-        if (p.active[d]) {
-            const int ud = d - (3 - p.ndim);  // user dimension
-            X[d] = axis_positions(p.n[d], coords ? coords[ud] : nullptr);
-        }
+        if (p.active[d]) X[d] = axis_positions(p.n[d], coords ? coords[p.udim[d]] : nullptr);
     std::vector<T> host;
     p.lv.resize((size_t)L);
     for (int k = 0; k < L; k++) {
@@ -274,16 +338,29 @@ int build_plan(Plan& p, const double* const* coords)
         for (int d = 0; d < 3; d++) {
             ly.m[d] = p.active[d] ? ((p.n[d] - 1) >> k) + 1 : 1;
             ly.mc[d] = p.active[d] ? (ly.m[d] + 1) / 2 : 1;
-            ly.w[d] = ly.K[d] = ly.lf[d] = ly.ip[d] = ly.up[d] = 0;
+            ly.w[d] = ly.K[d] = 0;
+            ly.sub[d] = ly.sup[d] = ly.lseg[d] = ly.ipseg[d] = ly.alpha[d] = ly.beta[d] = 0;
+            ly.sl[d] = ly.sip[d] = ly.su[d] = 0;
+            ly.S[d] = 1;
             if (!p.active[d]) continue;
             std::vector<double> y((size_t)ly.m[d]);
             for (int64_t j = 0; j < ly.m[d]; j++) y[(size_t)j] = X[d][(size_t)(j << k)];
             DimTab t = build_dim(y);
             push_table(host, t.w, &ly.w[d]);
             push_table(host, t.K, &ly.K[d]);
-            push_table(host, t.lf, &ly.lf[d]);
-            push_table(host, t.ip, &ly.ip[d]);
-            push_table(host, t.up, &ly.up[d]);
+            std::vector<double> yc((size_t)ly.mc[d]);
+            for (int64_t i = 0; i < ly.mc[d]; i++) yc[(size_t)i] = y[(size_t)(2 * i)];
+            SolveTab sv = build_solve(yc);
+            ly.S[d] = sv.S;
+            push_table(host, sv.sub, &ly.sub[d]);
+            push_table(host, sv.sup, &ly.sup[d]);
+            push_table(host, sv.lseg, &ly.lseg[d]);
+            push_table(host, sv.ipseg, &ly.ipseg[d]);
+            push_table(host, sv.alpha, &ly.alpha[d]);
+            push_table(host, sv.beta, &ly.beta[d]);
+            push_table(host, sv.sl, &ly.sl[d]);
+            push_table(host, sv.sip, &ly.sip[d]);
+            push_table(host, sv.su, &ly.su[d]);
         }
     }
     // workspace: W_1..W_L, load-vector ping-pong P1/P2, F, adjoint buffer Tb
@@ -311,6 +388,7 @@ int build_plan(Plan& p, const double* const* coords)
     p.P2 = off; off = align_up(off + P2, al);
     p.F = off;  off = align_up(off + Fn, al);
     p.Tb = off; off = align_up(off + (L > 0 ? (size_t)V0 : 0), al);
+    p.Yb = off; off = align_up(off + 2 * Fn / kSeg + 64, al);
     p.esize = sizeof(T);
     p.ws_bytes = off * sizeof(T);
     p.tables_bytes = host.size() * sizeof(T);
@@ -362,9 +440,15 @@ int get_plan(int dtype, int ndim, const int64_t* shape, const double* const* coo
     p->dtype = dtype;
     p->ndim = ndim;
     p->nlevels = nlevels;
-    for (int d = 0; d < ndim; d++) {
-        p->n[3 - ndim + d] = shape[d];
-        p->active[3 - ndim + d] = true;
+    // 3-D: (n0, n1, n2); 2-D: (n0, 1, n1) so the streaming kernel walks
+    // rows; 1-D: (1, 1, n0).
+    static const int kMap[4][3] = {{-1, -1, -1}, {-1, -1, 0}, {0, -1, 1}, {0, 1, 2}};
+    for (int d = 0; d < 3; d++) {
+        p->udim[d] = kMap[ndim][d];
+        if (p->udim[d] >= 0) {
+            p->n[d] = shape[p->udim[d]];
+            p->active[d] = true;
+        }
     }
     p->st[2] = 1;
     p->st[1] = p->n[2];
@@ -410,9 +494,6 @@ DimTables<T> tables_of(const Plan& p, int k)
         bool a = p.active[d];
         tb.w[d] = a ? base + ly.w[d] : nullptr;
         tb.K[d] = a ? base + ly.K[d] : nullptr;
-        tb.lf[d] = a ? base + ly.lf[d] : nullptr;
-        tb.ip[d] = a ? base + ly.ip[d] : nullptr;
-        tb.up[d] = a ? base + ly.up[d] : nullptr;
     }
     return tb;
 }
@@ -423,44 +504,70 @@ DimTables<T> tables_of(const Plan& p, int k)
         if (e_ != hipSuccess) return hip_fail(e_, what);   \
     } while (0)
 
-// Load vector f = R M vec(C) of level step k into F (packed coarse shape).
-// Dimensions last to first; the first pass masks the coarse nodes of C.
 template <typename T>
-int load_vector(const Plan& p, int k, const T* C, View3 cv, hipStream_t st)
+SolveTables<T> solve_tables_of(const Plan& p, int k, int d)
+{
+    const T* base = (const T*)p.tables;
+    const LevelLayout& ly = p.lv[(size_t)k];
+    SolveTables<T> t;
+    t.sub = base + ly.sub[d];
+    t.sup = base + ly.sup[d];
+    t.lseg = base + ly.lseg[d];
+    t.ipseg = base + ly.ipseg[d];
+    t.alpha = base + ly.alpha[d];
+    t.beta = base + ly.beta[d];
+    t.sl = base + ly.sl[d];
+    t.sip = base + ly.sip[d];
+    t.su = base + ly.su[d];
+    t.S = ly.S[d];
+    return t;
+}
+
+// Streaming level kernel: coefficients + load vector (dec) or load vector
+// from stored coefficients (!dec) of level step k; f goes to F.
+template <typename T>
+int stream_level(const Plan& p, int k, bool dec, const T* A, View3 av, T* C, View3 cv, T* W,
+                 bool write_coarse, hipStream_t st)
 {
     T* ws = (T*)p.ws;
-    DimTables<T> tb = tables_of<T>(p, k);
-    const T* in = C;
-    View3 iv = cv;
-    int64_t sh[3] = {cv.n[0], cv.n[1], cv.n[2]};
-    int npass = 0, done = 0;
-    for (int d = 0; d < 3; d++) npass += p.active[d];
-    for (int d = 2; d >= 0; d--) {
-        if (!p.active[d]) continue;
-        sh[d] = (sh[d] + 1) / 2;
-        T* out = (done == npass - 1) ? ws + p.F : (done == 0 ? ws + p.P1 : ws + p.P2);
-        View3 ov = packed(sh);
-        MGR_TRY(timed(KC_MASSTRANS, k, st,
-                      [&] { return launch_masstrans<T>(in, iv, out, ov, d, tb.K[d], done == 0, st); }),
-                "masstrans launch");
-        in = out;
-        iv = ov;
-        done++;
-    }
+    const LevelLayout& ly = p.lv[(size_t)k];
+    StreamArgs<T> a;
+    a.A = A;
+    a.av = av;
+    a.C = C;
+    a.cv = cv;
+    a.W = W;
+    a.wv = packed(ly.mc);
+    a.F = ws + p.F;
+    a.fv = packed(ly.mc);
+    a.tb = tables_of<T>(p, k);
+    a.write_coarse = write_coarse ? 1 : 0;
+    a.chunk = a.nt1 = a.nt2 = a.nch = 0;
+    MGR_TRY(timed(dec ? KC_STREAM_DEC : KC_STREAM_LOAD, k, st,
+                  [&] { return launch_stream_level<T>(a, dec, st); }),
+            "level kernel launch");
     return MGR_OK;
 }
 
+// Correction solves on F along every dimension; with W set, the last one
+// also adds sign * z to W (the coarse values).
 template <typename T>
-int solve_all(const Plan& p, int k, bool reverse, hipStream_t st)
+int solve_all(const Plan& p, int k, bool reverse, T* W, T sign, hipStream_t st)
 {
     T* ws = (T*)p.ws;
-    DimTables<T> tb = tables_of<T>(p, k);
     View3 fv = packed(p.lv[(size_t)k].mc);
+    int last = -1;
+    for (int s = 0; s < 3; s++) {
+        int d = reverse ? s : 2 - s;
+        if (p.active[d]) last = d;
+    }
     for (int s = 0; s < 3; s++) {
         int d = reverse ? s : 2 - s;
         if (!p.active[d]) continue;
+        SolveTables<T> tb = solve_tables_of<T>(p, k, d);
+        T* Wd = (d == last) ? W : nullptr;
         MGR_TRY(timed(KC_SOLVE, k, st,
-                      [&] { return launch_solve<T>(ws + p.F, fv, d, tb.lf[d], tb.ip[d], tb.up[d], st); }),
+                      [&] { return launch_solve_partitioned<T>(ws + p.F, fv, d, tb, ws + p.Yb, Wd, sign, st); }),
                 "solve launch");
     }
     return MGR_OK;
@@ -491,17 +598,22 @@ int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
         View3 av = (k == 0) ? full_view(p) : packed(ly.m);
         View3 cv = level_view(p, k);
         T* W = ws + p.Woff[(size_t)k + 1];
-        View3 wv = packed(ly.mc);
-        DimTables<T> tb = tables_of<T>(p, k);
-        MGR_TRY(timed(KC_COEF, k, st, [&] { return launch_coef_decompose<T>(A, av, dst, cv, W, wv, tb, st); }),
-                "coefficient launch");
-        int rc = load_vector<T>(p, k, dst, cv, st);
+        int rc;
+        if (k == 0 && (const void*)src == (const void*)dst) {
+            // In place: the streaming kernel's halos would read coefficients
+            // written by neighbouring tiles, so form the coefficients first
+            // (each node reads only coarse nodes) and then the load vector.
+            DimTables<T> tb = tables_of<T>(p, k);
+            View3 wv = packed(ly.mc);
+            MGR_TRY(timed(KC_COEF, k, st, [&] { return launch_coef_decompose<T>(A, av, dst, cv, W, wv, tb, st); }),
+                    "coefficient launch");
+            rc = stream_level<T>(p, k, false, dst, cv, nullptr, cv, nullptr, false, st);
+        } else {
+            rc = stream_level<T>(p, k, true, A, av, dst, cv, W, k == 0, st);
+        }
         if (rc) return rc;
-        rc = solve_all<T>(p, k, false, st);
+        rc = solve_all<T>(p, k, false, W, T(1), st);
         if (rc) return rc;
-        int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
-        MGR_TRY(timed(KC_APPLY, k, st, [&] { return launch_apply<T>(W, ws + p.F, nc, T(1), st); }),
-                "apply launch");
     }
     View3 cl = level_view(p, L);
     MGR_TRY(timed(KC_COPY_VIEW, L, st,
@@ -525,19 +637,24 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     for (int k = L - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
         View3 cv = level_view(p, k);
-        int rc = load_vector<T>(p, k, src, cv, st);
-        if (rc) return rc;
-        rc = solve_all<T>(p, k, false, st);
-        if (rc) return rc;
         T* W = ws + p.Woff[(size_t)k + 1];
-        int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
-        MGR_TRY(timed(KC_APPLY, k, st, [&] { return launch_apply<T>(W, ws + p.F, nc, T(-1), st); }),
-                "apply launch");
-        T* out = (k == 0) ? dst : ws + p.Woff[(size_t)k];
-        View3 ov = (k == 0) ? full_view(p) : packed(ly.m);
-        DimTables<T> tb = tables_of<T>(p, k);
-        MGR_TRY(timed(KC_INTERP, k, st,
-                      [&] { return launch_interp_recompose<T>(src, cv, out, ov, W, packed(ly.mc), tb, st); }),
+        int rc = stream_level<T>(p, k, false, src, cv, nullptr, cv, nullptr, false, st);
+        if (rc) return rc;
+        rc = solve_all<T>(p, k, false, W, T(-1), st);
+        if (rc) return rc;
+        StreamArgs<T> a;
+        a.A = src;
+        a.av = cv;
+        a.C = (k == 0) ? dst : ws + p.Woff[(size_t)k];
+        a.cv = (k == 0) ? full_view(p) : packed(ly.m);
+        a.W = W;
+        a.wv = packed(ly.mc);
+        a.F = nullptr;
+        a.fv = packed(ly.mc);
+        a.tb = tables_of<T>(p, k);
+        a.write_coarse = 0;
+        a.chunk = a.nt1 = a.nt2 = a.nch = 0;
+        MGR_TRY(timed(KC_INTERP, k, st, [&] { return launch_stream_recon<T>(a, st); }),
                 "interpolation launch");
     }
     return MGR_OK;
@@ -562,7 +679,7 @@ int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
         int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
         MGR_TRY(hipMemcpyAsync(ws + p.F, G, (size_t)nc * sizeof(T), hipMemcpyDeviceToDevice, st),
                 "adjoint copy");
-        int rc = solve_all<T>(p, k, true, st);
+        int rc = solve_all<T>(p, k, true, (T*)nullptr, T(0), st);
         if (rc) return rc;
         DimTables<T> tb = tables_of<T>(p, k);
         // t = (M P) y, dimensions first to last; the last pass adds g_f.
@@ -620,8 +737,8 @@ int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const in
 }
 
 const char* const kKernelNames[KC_COUNT] = {
-    "coef_decompose", "masstrans", "solve", "apply", "interp_recompose",
-    "masstrans_t", "adj_combine", "copy_view", "bench_copy"};
+    "coef_decompose", "solve", "interp_recompose",
+    "masstrans_t", "adj_combine", "copy_view", "bench_copy", "stream_dec", "stream_load"};
 
 }  // namespace
 }  // namespace mgr

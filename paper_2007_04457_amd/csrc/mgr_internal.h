@@ -21,45 +21,74 @@ struct View3 {
 //        w[2j+1] the upper one (a_j).
 //   K  : the merged mass-transfer stencil R M (Sec. III-A.2): 5 weights per
 //        coarse node i, K[5i + t + 2] multiplying fine node 2i + t.
-//   lf, ip, up : Thomas factors of the coarse mass matrix M_{l-1}: forward
-//        multipliers, inverse pivots and super-diagonal.
 template <typename T>
 struct DimTables {
     const T* w[3];
     const T* K[3];
-    const T* lf[3];
-    const T* ip[3];
-    const T* up[3];
 };
+
+// Arguments of the streaming level kernel (mgr_stream.hip).
+template <typename T>
+struct StreamArgs {
+    const T* A;  // level grid input (u, or coefficients)
+    View3 av;
+    T* C;  // coefficient output (decomposition only)
+    View3 cv;
+    T* W;  // packed coarse values (decomposition only)
+    View3 wv;
+    T* F;  // packed load vector
+    View3 fv;
+    DimTables<T> tb;
+    int write_coarse;  // also write u at coarse positions of C
+    int chunk, nt1, nt2, nch;  // filled in by the launcher
+};
+
+// Segment length of the partitioned Thomas solve (mgr_solve.hip).
+constexpr int kSeg = 32;
+
+// Tables of the partitioned solve for one (level, dimension), n coarse nodes:
+// per node the off-diagonals of M_{l-1} (sub couples i-1, sup couples i+1),
+// the segment-local Thomas factors and the separator responses alpha/beta;
+// per separator s = 1..S-1 the factors of the separator system.
+template <typename T>
+struct SolveTables {
+    const T* sub;
+    const T* sup;
+    const T* lseg;
+    const T* ipseg;
+    const T* alpha;
+    const T* beta;
+    const T* sl;
+    const T* sip;
+    const T* su;
+    int S;
+};
+
+template <typename T>
+hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
+template <typename T>
+hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st);
+template <typename T>
+hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, T* W, T sign,
+                                    hipStream_t st);
 
 // Kernel classes (for timing and profiling names).
 enum KernelClass {
     KC_COEF = 0,
-    KC_MASSTRANS,
     KC_SOLVE,
-    KC_APPLY,
     KC_INTERP,
     KC_MASSTRANS_T,
     KC_ADJ_COMBINE,
     KC_COPY_VIEW,
     KC_BENCH_COPY,
+    KC_STREAM_DEC,
+    KC_STREAM_LOAD,
     KC_COUNT
 };
 
 template <typename T>
 hipError_t launch_coef_decompose(const T* A, View3 av, T* C, View3 cv, T* W, View3 wv,
                                  DimTables<T> tb, hipStream_t st);
-template <typename T>
-hipError_t launch_masstrans(const T* X, View3 xv, T* Y, View3 yv, int d, const T* K,
-                            int mask_coarse, hipStream_t st);
-template <typename T>
-hipError_t launch_solve(T* F, View3 fv, int d, const T* lf, const T* ip, const T* up,
-                        hipStream_t st);
-template <typename T>
-hipError_t launch_apply(T* W, const T* F, int64_t n, T sign, hipStream_t st);
-template <typename T>
-hipError_t launch_interp_recompose(const T* C, View3 cv, T* Out, View3 ov, const T* W,
-                                   View3 wv, DimTables<T> tb, hipStream_t st);
 template <typename T>
 hipError_t launch_masstrans_t(const T* Y, View3 yv, T* X, View3 xv, int d, const T* K,
                               const T* add, View3 addv, int use_add, hipStream_t st);

@@ -111,100 +111,6 @@ k_coef_decompose(const T* A, View3 av, T* C, View3 cv,  // A and C may alias (in
     }
 }
 
-// One dimension of the load vector f = R M vec(C) (Sec. III-A.2, merged
-// "mass-trans" stencil): Y(.., i, ..) = sum_t K_i[t] X(.., 2i+t, ..).  With
-// mask_coarse, X values at nodes whose indices are all even read as zero
-// (C is zero on N_{l-1}).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_masstrans(const T* __restrict__ X, View3 xv, T* __restrict__ Y, View3 yv, int d,
-            const T* __restrict__ K, int mask_coarse, int64_t total)
-{
-    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kBlock) {
-        int64_t o[3];
-        decode3(idx, yv.n, o);
-        const int64_t i = o[d], m_in = xv.n[d];
-        int64_t j[3] = {o[0], o[1], o[2]};
-        int64_t oth = 0;
-#pragma unroll
-        for (int e = 0; e < 3; e++)
-            if (e != d) oth |= o[e];
-        const bool others_even = (oth & 1) == 0;
-        T s = T(0);
-#pragma unroll
-        for (int t = -2; t <= 2; t++) {
-            int64_t jd = 2 * i + t;
-            if (jd < 0 || jd >= m_in) continue;
-            j[d] = jd;
-            T v = X[at(xv, j[0], j[1], j[2])];
-            if (mask_coarse && others_even && ((jd & 1) == 0)) v = T(0);
-            s += K[5 * i + t + 2] * v;
-        }
-        Y[at(yv, o[0], o[1], o[2])] = s;
-    }
-}
-
-// Correction solve (Sec. II-A.2, Sec. III-A.3): one Thomas solve of the
-// coarse mass matrix per fibre along d, in place.  One thread per fibre.
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_solve(T* __restrict__ F, View3 fv, int d, const T* __restrict__ lf,
-        const T* __restrict__ ip, const T* __restrict__ up, int64_t nfib)
-{
-    const int da = (d == 0) ? 1 : 0;
-    const int db = (d == 2) ? 1 : 2;
-    const int64_t n = fv.n[d], sd = fv.s[d];
-    for (int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x; f < nfib;
-         f += (int64_t)gridDim.x * kBlock) {
-        const int64_t ja = f / fv.n[db], jb = f % fv.n[db];
-        T* p = F + ja * fv.s[da] + jb * fv.s[db];
-        T g = p[0];
-        for (int64_t i = 1; i < n; i++) {
-            g = p[i * sd] - lf[i] * g;
-            p[i * sd] = g;
-        }
-        T z = g * ip[n - 1];
-        p[(n - 1) * sd] = z;
-        for (int64_t i = n - 2; i >= 0; i--) {
-            z = (p[i * sd] - up[i] * z) * ip[i];
-            p[i * sd] = z;
-        }
-    }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_apply(T* __restrict__ W, const T* __restrict__ F, int64_t n, T sign)
-{
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        W[i] += sign * F[i];
-}
-
-// Recomposition of one level step: coarse nodes take the corrected coarse
-// values W, fine-only nodes c(p) + Pi u(p).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_interp_recompose(const T* C, View3 cv, T* Out, View3 ov,  // C and Out may alias
-                   const T* __restrict__ W, View3 wv, DimTables<T> tb, int64_t total)
-{
-    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kBlock) {
-        int64_t j[3];
-        decode3(idx, cv.n, j);
-        T r;
-        if (((j[0] | j[1] | j[2]) & 1) == 0) {
-            r = W[at(wv, j[0] >> 1, j[1] >> 1, j[2] >> 1)];
-        } else {
-            Corners<T> c;
-            corners(j, tb, c);
-            r = C[at(cv, j[0], j[1], j[2])] + interp_corners<T, true>(W, wv, c);
-        }
-        Out[at(ov, j[0], j[1], j[2])] = r;
-    }
-}
-
 // Transposed load-vector stencil along d: X(.., j, ..) = sum_i K_i[j-2i] Y(.., i, ..)
 // (the operator M P of the adjoint).  With use_add the addend is added at
 // fine-only nodes of the output grid.
@@ -308,43 +214,6 @@ hipError_t launch_coef_decompose(const T* A, View3 av, T* C, View3 cv, T* W, Vie
 }
 
 template <typename T>
-hipError_t launch_masstrans(const T* X, View3 xv, T* Y, View3 yv, int d, const T* K,
-                            int mask_coarse, hipStream_t st)
-{
-    int64_t total = vol(yv);
-    hipLaunchKernelGGL(k_masstrans<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, X, xv, Y,
-                       yv, d, K, mask_coarse, total);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_solve(T* F, View3 fv, int d, const T* lf, const T* ip, const T* up,
-                        hipStream_t st)
-{
-    int64_t nfib = vol(fv) / fv.n[d];
-    hipLaunchKernelGGL(k_solve<T>, dim3(grid_for(nfib)), dim3(kBlock), 0, st, F, fv, d, lf, ip,
-                       up, nfib);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_apply(T* W, const T* F, int64_t n, T sign, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_apply<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, W, F, n, sign);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_interp_recompose(const T* C, View3 cv, T* Out, View3 ov, const T* W,
-                                   View3 wv, DimTables<T> tb, hipStream_t st)
-{
-    int64_t total = vol(cv);
-    hipLaunchKernelGGL(k_interp_recompose<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, C,
-                       cv, Out, ov, W, wv, tb, total);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_masstrans_t(const T* Y, View3 yv, T* X, View3 xv, int d, const T* K,
                               const T* add, View3 addv, int use_add, hipStream_t st)
 {
@@ -384,13 +253,6 @@ hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStrea
 #define MGR_INSTANTIATE(T)                                                                      \
     template hipError_t launch_coef_decompose<T>(const T*, View3, T*, View3, T*, View3,         \
                                                  DimTables<T>, hipStream_t);                    \
-    template hipError_t launch_masstrans<T>(const T*, View3, T*, View3, int, const T*, int,     \
-                                            hipStream_t);                                       \
-    template hipError_t launch_solve<T>(T*, View3, int, const T*, const T*, const T*,           \
-                                        hipStream_t);                                           \
-    template hipError_t launch_apply<T>(T*, const T*, int64_t, T, hipStream_t);                 \
-    template hipError_t launch_interp_recompose<T>(const T*, View3, T*, View3, const T*, View3, \
-                                                   DimTables<T>, hipStream_t);                  \
     template hipError_t launch_masstrans_t<T>(const T*, View3, T*, View3, int, const T*,        \
                                               const T*, View3, int, hipStream_t);               \
     template hipError_t launch_adj_combine<T>(const T*, View3, T*, View3, const T*, View3,      \
