@@ -108,6 +108,13 @@ const char* mgr_last_error(void);
  * work that uses them is still in flight: synchronise first. */
 void mgr_finalize(void);
 
+/* Level steps whose level grid has at most `max_nodes` nodes run together in
+ * one single-workgroup launch (the small coarse levels are launch-bound);
+ * larger steps use one streaming launch plus one solve launch per
+ * dimension.  Default 5000; 0 disables the combined launch.  Returns the
+ * previous value.  Process-wide; affects calls enqueued afterwards. */
+int64_t mgr_set_tail_max_nodes(int64_t max_nodes);
+
 /* ---- measurement support ------------------------------------------------
  * The single-pass copy kernel the paper uses to define achievable
  * bandwidth (Sec. IV-C): dst[i] = src[i] for nbytes (a multiple of 16,

@@ -17,7 +17,7 @@ from ._lib import MgrError, MGR_F32, MGR_F64
 __all__ = [
     "MgrError", "MGR_F32", "MGR_F64",
     "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_prepare",
-    "mgr_class_map", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize",
+    "mgr_class_map", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
     "decompose", "recompose", "decompose_adjoint", "Decompose", "kernel_classes",
 ]
@@ -115,6 +115,12 @@ def mgr_bench_copy(src, dst):
     stream = torch.cuda.current_stream(src.device).cuda_stream
     _lib.check(_lib.load().mgr_bench_copy(src.data_ptr(), dst.data_ptr(), n, stream))
     return dst
+
+
+def mgr_set_tail_max_nodes(max_nodes):
+    """Level steps with at most max_nodes nodes share one launch; returns
+    the previous setting (0 disables)."""
+    return _lib.load().mgr_set_tail_max_nodes(int(max_nodes))
 
 
 def mgr_finalize():

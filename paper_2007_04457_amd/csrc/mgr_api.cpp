@@ -8,6 +8,7 @@
 // (m_d + 1) / 2, which the driver keeps packed in workspace buffers W_{k+1}.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -44,8 +45,9 @@ constexpr int kMaxDim = 3;
 // its tables inside the plan's device table buffer (inactive dims unused).
 struct LevelLayout {
     int64_t m[3], mc[3];
-    size_t w[3], K[3];
-    size_t sub[3], sup[3], lseg[3], ipseg[3], alpha[3], beta[3], sl[3], sip[3], su[3];
+    size_t w[3], K[3], lf[3], ip[3];  // lf, ip: plain Thomas factors of M_{l-1}
+    size_t sup[3];  // plain super-diagonal of M_{l-1}
+    size_t L[3], U[3], IP[3], A[3], B[3], ssub[3], ssup[3], sl[3], sip[3], su[3];
     int S[3];
 };
 
@@ -60,7 +62,7 @@ struct Plan {
     void* ws = nullptr;
     size_t ws_bytes = 0, tables_bytes = 0, esize = 4;
     std::vector<size_t> Woff;  // W_k element offsets, k = 1..L (index k)
-    size_t P1 = 0, P2 = 0, F = 0, Tb = 0, Yb = 0;
+    size_t P1 = 0, P2 = 0, F = 0, F2 = 0, Tb = 0, Yb = 0;  // F, F2: corrections of even, odd level steps
 };
 
 std::mutex g_mu;
@@ -209,7 +211,9 @@ DimTab build_dim(const std::vector<double>& y)
 }
 
 struct SolveTab {
-    std::vector<double> sub, sup, lseg, ipseg, alpha, beta, sl, sip, su;
+    std::vector<double> sub, sup;                  // plain off-diagonals, length n
+    std::vector<double> L, U, IP, A, B;            // padded, S * kSlot
+    std::vector<double> ssub, ssup, sl, sip, su;   // per separator, length S
     int S = 1;
 };
 
@@ -231,60 +235,78 @@ SolveTab build_solve(const std::vector<double>& yc)
     // n - 1 is a power of two, so it is a multiple of kSeg once >= kSeg
     t.S = (n - 1 >= kSeg) ? (int)((n - 1) / kSeg) : 1;
     const int S = t.S;
-    t.lseg.assign((size_t)n, 0.0);
-    t.ipseg.assign((size_t)n, 0.0);
-    t.alpha.assign((size_t)n, 0.0);
-    t.beta.assign((size_t)n, 0.0);
+    const size_t P = (size_t)S * kSlot;
+    t.L.assign(P, 0.0);
+    t.U.assign(P, 0.0);
+    t.IP.assign(P, 0.0);
+    t.A.assign(P, 0.0);
+    t.B.assign(P, 0.0);
+    std::vector<double> alpha((size_t)n, 0.0), beta((size_t)n, 0.0);
     for (int s = 0; s < S; s++) {
         const int64_t lo = (int64_t)s * kSeg + (s > 0 ? 1 : 0);
         const int64_t hi = (s == S - 1) ? n : (int64_t)(s + 1) * kSeg;
+        std::vector<double> lf((size_t)(hi - lo), 0.0), ip((size_t)(hi - lo), 0.0);
         double den = 0.0;
         for (int64_t i = lo; i < hi; i++) {
+            const size_t q = (size_t)(i - lo);
             if (i == lo) {
                 den = diag[(size_t)i];
             } else {
-                t.lseg[(size_t)i] = t.sub[(size_t)i] / den;
-                den = diag[(size_t)i] - t.lseg[(size_t)i] * t.sup[(size_t)(i - 1)];
+                lf[q] = t.sub[(size_t)i] / den;
+                den = diag[(size_t)i] - lf[q] * t.sup[(size_t)(i - 1)];
             }
-            t.ipseg[(size_t)i] = 1.0 / den;
+            ip[q] = 1.0 / den;
         }
         auto local_solve = [&](std::vector<double>& v) {
-            for (int64_t i = lo + 1; i < hi; i++) v[(size_t)i] -= t.lseg[(size_t)i] * v[(size_t)(i - 1)];
+            for (int64_t i = lo + 1; i < hi; i++) v[(size_t)i] -= lf[(size_t)(i - lo)] * v[(size_t)(i - 1)];
             for (int64_t i = hi - 1; i >= lo; i--) {
                 double z = (i == hi - 1) ? 0.0 : v[(size_t)(i + 1)];
-                v[(size_t)i] = (v[(size_t)i] - t.sup[(size_t)i] * z) * t.ipseg[(size_t)i];
+                v[(size_t)i] = (v[(size_t)i] - t.sup[(size_t)i] * z) * ip[(size_t)(i - lo)];
             }
         };
         if (s > 0) {
             std::vector<double> v((size_t)n, 0.0);
             v[(size_t)lo] = -t.sub[(size_t)lo];
             local_solve(v);
-            for (int64_t i = lo; i < hi; i++) t.alpha[(size_t)i] = v[(size_t)i];
+            for (int64_t i = lo; i < hi; i++) alpha[(size_t)i] = v[(size_t)i];
         }
         if (s < S - 1) {
             std::vector<double> v((size_t)n, 0.0);
             v[(size_t)(hi - 1)] = -t.sup[(size_t)(hi - 1)];
             local_solve(v);
-            for (int64_t i = lo; i < hi; i++) t.beta[(size_t)i] = v[(size_t)i];
+            for (int64_t i = lo; i < hi; i++) beta[(size_t)i] = v[(size_t)i];
+        }
+        for (int64_t i = lo; i < hi; i++) {
+            const size_t q = (size_t)s * kSlot + (size_t)(i - lo);
+            t.L[q] = lf[(size_t)(i - lo)];
+            // the segment's last row has no coupling inside the segment
+            t.U[q] = (i == hi - 1) ? 0.0 : t.sup[(size_t)i];
+            t.IP[q] = ip[(size_t)(i - lo)];
+            t.A[q] = alpha[(size_t)i];
+            t.B[q] = beta[(size_t)i];
         }
     }
+    t.ssub.assign((size_t)S, 0.0);
+    t.ssup.assign((size_t)S, 0.0);
     t.sl.assign((size_t)S, 0.0);
     t.sip.assign((size_t)S, 0.0);
     t.su.assign((size_t)S, 0.0);
     double den = 0.0;
     for (int s = 1; s < S; s++) {
         const int64_t p = (int64_t)s * kSeg;
-        const double L = t.sub[(size_t)p] * t.alpha[(size_t)(p - 1)];
-        const double D = diag[(size_t)p] + t.sub[(size_t)p] * t.beta[(size_t)(p - 1)] +
-                         t.sup[(size_t)p] * t.alpha[(size_t)(p + 1)];
-        const double U = t.sup[(size_t)p] * t.beta[(size_t)(p + 1)];
+        t.ssub[(size_t)s] = t.sub[(size_t)p];
+        t.ssup[(size_t)s] = t.sup[(size_t)p];
+        const double Lc = t.sub[(size_t)p] * alpha[(size_t)(p - 1)];
+        const double D = diag[(size_t)p] + t.sub[(size_t)p] * beta[(size_t)(p - 1)] +
+                         t.sup[(size_t)p] * alpha[(size_t)(p + 1)];
+        const double Uc = t.sup[(size_t)p] * beta[(size_t)(p + 1)];
         if (s == 1) {
             den = D;
         } else {
-            t.sl[(size_t)s] = L / den;
+            t.sl[(size_t)s] = Lc / den;
             den = D - t.sl[(size_t)s] * t.su[(size_t)(s - 1)];
         }
-        t.su[(size_t)s] = U;
+        t.su[(size_t)s] = Uc;
         t.sip[(size_t)s] = 1.0 / den;
     }
     return t;
@@ -338,9 +360,9 @@ int build_plan(Plan& p, const double* const* coords)
         for (int d = 0; d < 3; d++) {
             ly.m[d] = p.active[d] ? ((p.n[d] - 1) >> k) + 1 : 1;
             ly.mc[d] = p.active[d] ? (ly.m[d] + 1) / 2 : 1;
-            ly.w[d] = ly.K[d] = 0;
-            ly.sub[d] = ly.sup[d] = ly.lseg[d] = ly.ipseg[d] = ly.alpha[d] = ly.beta[d] = 0;
-            ly.sl[d] = ly.sip[d] = ly.su[d] = 0;
+            ly.w[d] = ly.K[d] = ly.lf[d] = ly.ip[d] = 0;
+            ly.sup[d] = ly.L[d] = ly.U[d] = ly.IP[d] = ly.A[d] = ly.B[d] = 0;
+            ly.ssub[d] = ly.ssup[d] = ly.sl[d] = ly.sip[d] = ly.su[d] = 0;
             ly.S[d] = 1;
             if (!p.active[d]) continue;
             std::vector<double> y((size_t)ly.m[d]);
@@ -351,13 +373,33 @@ int build_plan(Plan& p, const double* const* coords)
             std::vector<double> yc((size_t)ly.mc[d]);
             for (int64_t i = 0; i < ly.mc[d]; i++) yc[(size_t)i] = y[(size_t)(2 * i)];
             SolveTab sv = build_solve(yc);
+            {
+                // plain Thomas factors of the whole coarse fibre (small levels)
+                const size_t nc = yc.size();
+                std::vector<double> lf(nc, 0.0), ip(nc, 0.0);
+                double den = 0.0;
+                for (size_t i = 0; i < nc; i++) {
+                    const double diag = 2.0 * (sv.sub[i] + sv.sup[i]);
+                    if (i == 0) {
+                        den = diag;
+                    } else {
+                        lf[i] = sv.sub[i] / den;
+                        den = diag - lf[i] * sv.sup[i - 1];
+                    }
+                    ip[i] = 1.0 / den;
+                }
+                push_table(host, lf, &ly.lf[d]);
+                push_table(host, ip, &ly.ip[d]);
+            }
             ly.S[d] = sv.S;
-            push_table(host, sv.sub, &ly.sub[d]);
             push_table(host, sv.sup, &ly.sup[d]);
-            push_table(host, sv.lseg, &ly.lseg[d]);
-            push_table(host, sv.ipseg, &ly.ipseg[d]);
-            push_table(host, sv.alpha, &ly.alpha[d]);
-            push_table(host, sv.beta, &ly.beta[d]);
+            push_table(host, sv.L, &ly.L[d]);
+            push_table(host, sv.U, &ly.U[d]);
+            push_table(host, sv.IP, &ly.IP[d]);
+            push_table(host, sv.A, &ly.A[d]);
+            push_table(host, sv.B, &ly.B[d]);
+            push_table(host, sv.ssub, &ly.ssub[d]);
+            push_table(host, sv.ssup, &ly.ssup[d]);
             push_table(host, sv.sl, &ly.sl[d]);
             push_table(host, sv.sip, &ly.sip[d]);
             push_table(host, sv.su, &ly.su[d]);
@@ -387,6 +429,12 @@ int build_plan(Plan& p, const double* const* coords)
     p.P1 = off; off = align_up(off + P1, al);
     p.P2 = off; off = align_up(off + P2, al);
     p.F = off;  off = align_up(off + Fn, al);
+    {
+        int64_t v1 = 1;
+        for (int d = 0; d < 3; d++) v1 *= p.active[d] ? ((p.n[d] - 1) >> 2) + 1 : 1;
+        p.F2 = off;
+        off = align_up(off + (L > 1 ? (size_t)v1 : 0), al);
+    }
     p.Tb = off; off = align_up(off + (L > 0 ? (size_t)V0 : 0), al);
     p.Yb = off; off = align_up(off + 2 * Fn / kSeg + 64, al);
     p.esize = sizeof(T);
@@ -510,12 +558,13 @@ SolveTables<T> solve_tables_of(const Plan& p, int k, int d)
     const T* base = (const T*)p.tables;
     const LevelLayout& ly = p.lv[(size_t)k];
     SolveTables<T> t;
-    t.sub = base + ly.sub[d];
-    t.sup = base + ly.sup[d];
-    t.lseg = base + ly.lseg[d];
-    t.ipseg = base + ly.ipseg[d];
-    t.alpha = base + ly.alpha[d];
-    t.beta = base + ly.beta[d];
+    t.L = base + ly.L[d];
+    t.U = base + ly.U[d];
+    t.IP = base + ly.IP[d];
+    t.A = base + ly.A[d];
+    t.B = base + ly.B[d];
+    t.ssub = base + ly.ssub[d];
+    t.ssup = base + ly.ssup[d];
     t.sl = base + ly.sl[d];
     t.sip = base + ly.sip[d];
     t.su = base + ly.su[d];
@@ -523,22 +572,31 @@ SolveTables<T> solve_tables_of(const Plan& p, int k, int d)
     return t;
 }
 
-// Streaming level kernel: coefficients + load vector (dec) or load vector
-// from stored coefficients (!dec) of level step k; f goes to F.
+// Correction buffer of level step k (even and odd steps alternate so that a
+// step can read the previous step's correction while writing its own).
 template <typename T>
-int stream_level(const Plan& p, int k, bool dec, const T* A, View3 av, T* C, View3 cv, T* W,
-                 bool write_coarse, hipStream_t st)
+T* corr(const Plan& p, int k)
 {
-    T* ws = (T*)p.ws;
+    return (T*)p.ws + ((k & 1) ? p.F2 : p.F);
+}
+
+// Streaming level kernel of level step k: coefficients + load vector (dec,
+// input A + Z) or the load vector from stored coefficients (!dec); the load
+// vector goes to corr(k).
+template <typename T>
+int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 av, T* C, View3 cv,
+                 T* W, bool write_coarse, hipStream_t st)
+{
     const LevelLayout& ly = p.lv[(size_t)k];
     StreamArgs<T> a;
     a.A = A;
+    a.Z = Z;
     a.av = av;
     a.C = C;
     a.cv = cv;
     a.W = W;
     a.wv = packed(ly.mc);
-    a.F = ws + p.F;
+    a.F = corr<T>(p, k);
     a.fv = packed(ly.mc);
     a.tb = tables_of<T>(p, k);
     a.write_coarse = write_coarse ? 1 : 0;
@@ -549,25 +607,18 @@ int stream_level(const Plan& p, int k, bool dec, const T* A, View3 av, T* C, Vie
     return MGR_OK;
 }
 
-// Correction solves on F along every dimension; with W set, the last one
-// also adds sign * z to W (the coarse values).
+// Correction solves of level step k on F along every dimension, in place.
 template <typename T>
-int solve_all(const Plan& p, int k, bool reverse, T* W, T sign, hipStream_t st)
+int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st)
 {
     T* ws = (T*)p.ws;
     View3 fv = packed(p.lv[(size_t)k].mc);
-    int last = -1;
-    for (int s = 0; s < 3; s++) {
-        int d = reverse ? s : 2 - s;
-        if (p.active[d]) last = d;
-    }
     for (int s = 0; s < 3; s++) {
         int d = reverse ? s : 2 - s;
         if (!p.active[d]) continue;
         SolveTables<T> tb = solve_tables_of<T>(p, k, d);
-        T* Wd = (d == last) ? W : nullptr;
         MGR_TRY(timed(KC_SOLVE, k, st,
-                      [&] { return launch_solve_partitioned<T>(ws + p.F, fv, d, tb, ws + p.Yb, Wd, sign, st); }),
+                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, ws + p.Yb, st); }),
                 "solve launch");
     }
     return MGR_OK;
@@ -584,6 +635,80 @@ int identity_copy(const Plan& p, const void* src, void* dst, hipStream_t st)
     return MGR_OK;
 }
 
+// First level step handled by the single-workgroup tail kernel: the finest
+// step whose level grid is small, but no more than kMaxTail steps.
+std::atomic<int64_t> g_tail_nodes{kTailMaxNodes};
+
+// LDS elements the tail kernel needs for level step k: level grid, the
+// load-vector passes, correction and coarse values; and for its tables.
+int64_t tail_data_elems(const Plan& p, int k)
+{
+    const LevelLayout& ly = p.lv[(size_t)k];
+    int64_t sh[3] = {ly.m[0], ly.m[1], ly.m[2]};
+    const int64_t V = sh[0] * sh[1] * sh[2], Vc = ly.mc[0] * ly.mc[1] * ly.mc[2];
+    int64_t tot = V + 2 * Vc, pass = 0;
+    for (int d = 2; d >= 0; d--) {
+        if (!p.active[d]) continue;
+        sh[d] = ly.mc[d];
+        if (++pass < 3 && sh[0] * sh[1] * sh[2] != Vc) tot += sh[0] * sh[1] * sh[2];
+    }
+    return tot;
+}
+
+int64_t tail_tab_elems(const Plan& p, int k)
+{
+    const LevelLayout& ly = p.lv[(size_t)k];
+    int64_t tot = 0;
+    for (int d = 0; d < 3; d++)
+        if (p.active[d]) tot += 2 * ly.m[d] + 8 * ly.mc[d];
+    return tot;
+}
+
+// First level step handled by the tail kernel: the finest step such that it
+// and every coarser step are small, at most kMaxTail steps.
+int tail_start(const Plan& p)
+{
+    const int L = p.nlevels;
+    const int64_t limit = g_tail_nodes.load();
+    int k = L;
+    while (k > 0 && L - (k - 1) <= kMaxTail) {
+        const LevelLayout& ly = p.lv[(size_t)(k - 1)];
+        if (ly.m[0] * ly.m[1] * ly.m[2] > limit) break;
+        if (tail_data_elems(p, k - 1) > kTailDataElems || tail_tab_elems(p, k - 1) > kTailTabElems) break;
+        k--;
+    }
+    return k;
+}
+
+template <typename T>
+TailArgs<T> tail_args(const Plan& p, int k0, const T* src, T* dst)
+{
+    TailArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    T* ws = (T*)p.ws;
+    const T* base = (const T*)p.tables;
+    a.k0 = k0;
+    a.nlev = p.nlevels - k0;
+    for (int d = 0; d < 3; d++) a.st[d] = p.st[d];
+    a.src = src;
+    a.dst = dst;
+    for (int l = 0; l < a.nlev; l++) {
+        const int k = k0 + l;
+        const LevelLayout& ly = p.lv[(size_t)k];
+        TailLevel<T>& t = a.lv[l];
+        for (int d = 0; d < 3; d++) {
+            t.m[d] = (int)ly.m[d];
+            t.mc[d] = (int)ly.mc[d];
+            t.lf[d] = p.active[d] ? base + ly.lf[d] : nullptr;
+            t.ip[d] = p.active[d] ? base + ly.ip[d] : nullptr;
+            t.up[d] = p.active[d] ? base + ly.sup[d] : nullptr;
+        }
+        t.tb = tables_of<T>(p, k);
+        t.Wk = (k == 0) ? nullptr : ws + p.Woff[(size_t)k];
+    }
+    return a;
+}
+
 template <typename T>
 int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
@@ -592,9 +717,12 @@ int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     const T* src = (const T*)src_;
     T* dst = (T*)dst_;
     T* ws = (T*)p.ws;
-    for (int k = 0; k < L; k++) {
+    const int kt = tail_start(p);
+    for (int k = 0; k < kt; k++) {
         const LevelLayout& ly = p.lv[(size_t)k];
+        // level grid k: the input, or the previous step's coarse values plus its correction
         const T* A = (k == 0) ? src : ws + p.Woff[(size_t)k];
+        const T* Z = (k == 0) ? nullptr : corr<T>(p, k - 1);
         View3 av = (k == 0) ? full_view(p) : packed(ly.m);
         View3 cv = level_view(p, k);
         T* W = ws + p.Woff[(size_t)k + 1];
@@ -607,17 +735,23 @@ int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             View3 wv = packed(ly.mc);
             MGR_TRY(timed(KC_COEF, k, st, [&] { return launch_coef_decompose<T>(A, av, dst, cv, W, wv, tb, st); }),
                     "coefficient launch");
-            rc = stream_level<T>(p, k, false, dst, cv, nullptr, cv, nullptr, false, st);
+            rc = stream_level<T>(p, k, false, dst, nullptr, cv, nullptr, cv, nullptr, false, st);
         } else {
-            rc = stream_level<T>(p, k, true, A, av, dst, cv, W, k == 0, st);
+            rc = stream_level<T>(p, k, true, A, Z, av, dst, cv, W, k == 0, st);
         }
         if (rc) return rc;
-        rc = solve_all<T>(p, k, false, W, T(1), st);
+        rc = solve_all<T>(p, k, false, corr<T>(p, k), st);
         if (rc) return rc;
+    }
+    if (kt < L) {
+        TailArgs<T> a = tail_args<T>(p, kt, src, dst);
+        a.Z0 = (kt == 0) ? nullptr : corr<T>(p, kt - 1);
+        MGR_TRY(timed(KC_TAIL, kt, st, [&] { return launch_tail<T>(a, true, st); }), "tail launch");
+        return MGR_OK;
     }
     View3 cl = level_view(p, L);
     MGR_TRY(timed(KC_COPY_VIEW, L, st,
-                  [&] { return launch_copy_view<T>(ws + p.Woff[(size_t)L], packed(cl.n), dst, cl, st); }),
+                  [&] { return launch_copy_view<T>(ws + p.Woff[(size_t)L], corr<T>(p, L - 1), packed(cl.n), dst, cl, st); }),
             "coarsest scatter");
     return MGR_OK;
 }
@@ -630,24 +764,31 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     const T* src = (const T*)src_;
     T* dst = (T*)dst_;
     T* ws = (T*)p.ws;
-    View3 cl = level_view(p, L);
-    MGR_TRY(timed(KC_COPY_VIEW, L, st,
-                  [&] { return launch_copy_view<T>(src, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
-            "coarsest gather");
-    for (int k = L - 1; k >= 0; k--) {
+    const int kt = tail_start(p);
+    if (kt < L) {
+        TailArgs<T> a = tail_args<T>(p, kt, src, dst);
+        a.Z0 = nullptr;
+        MGR_TRY(timed(KC_TAIL, kt, st, [&] { return launch_tail<T>(a, false, st); }), "tail launch");
+    } else {
+        View3 cl = level_view(p, L);
+        MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                      [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
+                "coarsest gather");
+    }
+    for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
         View3 cv = level_view(p, k);
-        T* W = ws + p.Woff[(size_t)k + 1];
-        int rc = stream_level<T>(p, k, false, src, cv, nullptr, cv, nullptr, false, st);
+        int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, st);
         if (rc) return rc;
-        rc = solve_all<T>(p, k, false, W, T(-1), st);
+        rc = solve_all<T>(p, k, false, corr<T>(p, k), st);
         if (rc) return rc;
         StreamArgs<T> a;
         a.A = src;
+        a.Z = corr<T>(p, k);
         a.av = cv;
         a.C = (k == 0) ? dst : ws + p.Woff[(size_t)k];
         a.cv = (k == 0) ? full_view(p) : packed(ly.m);
-        a.W = W;
+        a.W = ws + p.Woff[(size_t)k + 1];
         a.wv = packed(ly.mc);
         a.F = nullptr;
         a.fv = packed(ly.mc);
@@ -670,7 +811,7 @@ int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     T* ws = (T*)p.ws;
     View3 cl = level_view(p, L);
     MGR_TRY(timed(KC_COPY_VIEW, L, st,
-                  [&] { return launch_copy_view<T>(src, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
+                  [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
             "coarsest gather");
     for (int k = L - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
@@ -679,7 +820,7 @@ int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
         int64_t nc = ly.mc[0] * ly.mc[1] * ly.mc[2];
         MGR_TRY(hipMemcpyAsync(ws + p.F, G, (size_t)nc * sizeof(T), hipMemcpyDeviceToDevice, st),
                 "adjoint copy");
-        int rc = solve_all<T>(p, k, true, (T*)nullptr, T(0), st);
+        int rc = solve_all<T>(p, k, true, ws + p.F, st);
         if (rc) return rc;
         DimTables<T> tb = tables_of<T>(p, k);
         // t = (M P) y, dimensions first to last; the last pass adds g_f.
@@ -738,7 +879,7 @@ int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const in
 
 const char* const kKernelNames[KC_COUNT] = {
     "coef_decompose", "solve", "interp_recompose",
-    "masstrans_t", "adj_combine", "copy_view", "bench_copy", "stream_dec", "stream_load"};
+    "masstrans_t", "adj_combine", "copy_view", "bench_copy", "stream_dec", "stream_load", "tail"};
 
 }  // namespace
 }  // namespace mgr
@@ -860,6 +1001,12 @@ void mgr_finalize(void)
     }
     g_tm.ev.clear();
     g_tm.on = false;
+}
+
+int64_t mgr_set_tail_max_nodes(int64_t max_nodes)
+{
+    if (max_nodes < 0) max_nodes = 0;
+    return g_tail_nodes.exchange(max_nodes);
 }
 
 int mgr_bench_copy(const void* src, void* dst, size_t nbytes, void* stream)

@@ -31,6 +31,8 @@ struct DimTables {
 template <typename T>
 struct StreamArgs {
     const T* A;  // level grid input (u, or coefficients)
+    const T* Z;  // decomposition: correction added to A on load (or null);
+                 // recomposition: correction subtracted from W on load
     View3 av;
     T* C;  // coefficient output (decomposition only)
     View3 cv;
@@ -43,34 +45,73 @@ struct StreamArgs {
     int chunk, nt1, nt2, nch;  // filled in by the launcher
 };
 
-// Segment length of the partitioned Thomas solve (mgr_solve.hip).
+// Segment length of the partitioned Thomas solve (mgr_solve.hip); segment
+// tables are padded to kSlot entries.
 constexpr int kSeg = 32;
+constexpr int kSlot = kSeg + 1;
 
-// Tables of the partitioned solve for one (level, dimension), n coarse nodes:
-// per node the off-diagonals of M_{l-1} (sub couples i-1, sup couples i+1),
-// the segment-local Thomas factors and the separator responses alpha/beta;
-// per separator s = 1..S-1 the factors of the separator system.
+// Tables of the partitioned solve for one (level, dimension) with S segments:
+// per segment s and slot q (index s * kSlot + q, zero past the segment) the
+// local Thomas forward multipliers L, super-diagonal U, inverse pivots IP and
+// separator responses A (left) and B (right); per separator k = 1..S-1 the
+// matrix entries coupling it to its neighbours (ssub, ssup) and the Thomas
+// factors of the separator system (sl, sip, su).
 template <typename T>
 struct SolveTables {
-    const T* sub;
-    const T* sup;
-    const T* lseg;
-    const T* ipseg;
-    const T* alpha;
-    const T* beta;
+    const T* L;
+    const T* U;
+    const T* IP;
+    const T* A;
+    const T* B;
+    const T* ssub;
+    const T* ssup;
     const T* sl;
     const T* sip;
     const T* su;
     int S;
 };
 
+// In-place correction solve of F along dimension d.
+template <typename T>
+hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st);
+
+// Single-workgroup kernel for the small coarse levels (mgr_tail.hip): all
+// level steps k0 .. k0 + nlev - 1 in one launch, in LDS.  A level step may
+// join it when its level grid, load-vector passes, correction and coarse
+// values fit kTailDataElems elements and its tables kTailTabElems.
+constexpr int kTailThreads = 1024;
+constexpr int kMaxTail = 16;
+constexpr int64_t kTailMaxNodes = 5000;
+constexpr int kTailDataElems = 11264;
+constexpr int kTailTabElems = 3200;
+
+template <typename T>
+struct TailLevel {
+    int m[3], mc[3];  // level grid and coarse sizes (1 for inactive dims)
+    DimTables<T> tb;  // interpolation weights and stencils
+    const T* lf[3];   // plain Thomas factors of M_{l-1}: multipliers,
+    const T* ip[3];   // inverse pivots
+    const T* up[3];   // and super-diagonal
+    T* Wk;            // packed level grid k in the workspace (k > 0)
+};
+
+template <typename T>
+struct TailArgs {
+    TailLevel<T> lv[kMaxTail];  // index k - k0
+    int k0, nlev;
+    int64_t st[3];  // element strides of the user arrays
+    const T* src;   // user input
+    T* dst;         // user output
+    const T* Z0;    // decomposition: correction added to the level-k0 input (or null)
+};
+
+template <typename T>
+hipError_t launch_tail(const TailArgs<T>& a, bool decompose, hipStream_t st);
+
 template <typename T>
 hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
 template <typename T>
 hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st);
-template <typename T>
-hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, T* W, T sign,
-                                    hipStream_t st);
 
 // Kernel classes (for timing and profiling names).
 enum KernelClass {
@@ -83,6 +124,7 @@ enum KernelClass {
     KC_BENCH_COPY,
     KC_STREAM_DEC,
     KC_STREAM_LOAD,
+    KC_TAIL,
     KC_COUNT
 };
 
@@ -96,7 +138,7 @@ template <typename T>
 hipError_t launch_adj_combine(const T* Tb, View3 tv, T* Out, View3 ov, const T* G,
                               View3 gv, DimTables<T> tb, hipStream_t st);
 template <typename T>
-hipError_t launch_copy_view(const T* X, View3 xv, T* Y, View3 yv, hipStream_t st);
+hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hipStream_t st);
 
 hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStream_t st);
 

@@ -179,15 +179,19 @@ k_adj_combine(const T* __restrict__ Tb, View3 tv, T* __restrict__ Out, View3 ov,
     }
 }
 
+// Y = X (+ Z, with Z laid out like X when given): gathers and scatters of
+// the coarsest grid between the caller's array and the workspace.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_copy_view(const T* __restrict__ X, View3 xv, T* __restrict__ Y, View3 yv, int64_t total)
+k_copy_view(const T* __restrict__ X, const T* __restrict__ Z, View3 xv, T* __restrict__ Y, View3 yv,
+            int64_t total)
 {
     for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * kBlock) {
         int64_t j[3];
         decode3(idx, yv.n, j);
-        Y[at(yv, j[0], j[1], j[2])] = X[at(xv, j[0], j[1], j[2])];
+        const int64_t xo = at(xv, j[0], j[1], j[2]);
+        Y[at(yv, j[0], j[1], j[2])] = Z ? X[xo] + Z[xo] : X[xo];
     }
 }
 
@@ -234,10 +238,10 @@ hipError_t launch_adj_combine(const T* Tb, View3 tv, T* Out, View3 ov, const T* 
 }
 
 template <typename T>
-hipError_t launch_copy_view(const T* X, View3 xv, T* Y, View3 yv, hipStream_t st)
+hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hipStream_t st)
 {
     int64_t total = vol(yv);
-    hipLaunchKernelGGL(k_copy_view<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, X, xv, Y,
+    hipLaunchKernelGGL(k_copy_view<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, X, Z, xv, Y,
                        yv, total);
     return hipGetLastError();
 }
@@ -257,7 +261,7 @@ hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStrea
                                               const T*, View3, int, hipStream_t);               \
     template hipError_t launch_adj_combine<T>(const T*, View3, T*, View3, const T*, View3,      \
                                               DimTables<T>, hipStream_t);                       \
-    template hipError_t launch_copy_view<T>(const T*, View3, T*, View3, hipStream_t);
+    template hipError_t launch_copy_view<T>(const T*, const T*, View3, T*, View3, hipStream_t);
 
 MGR_INSTANTIATE(float)
 MGR_INSTANTIATE(double)

@@ -55,7 +55,7 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
 
 constexpr int kMaxChunk = 64;  // coarse planes per workgroup (LDS tables)
 
-template <typename T, bool kAct0, bool kAct1, int kT1, int kT2, bool kDec>
+template <typename T, bool kAct0, bool kAct1, int kT1, int kT2, bool kDec, bool kZ>
 __global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
 {
     static_assert(kT1 * kT2 == kThreads, "one coarse column per thread");
@@ -156,11 +156,16 @@ __global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
         aoff[q] = ok ? (R0 + r) * as1 + (C0 + c) * as2 : R0 * as1 + C0 * as2;
     }
 
-    T pre[NS];
+    // kZ: the input level grid is A + Z (coarse values plus the correction
+    // of the previous level step, added here instead of in a separate pass)
+    T pre[NS], preZ[NS];
     {
-        const T* base = a.A + (int64_t)plane_of(0) * a.av.s[0];
+        const int64_t po = (int64_t)plane_of(0) * a.av.s[0];
 #pragma unroll
-        for (int q = 0; q < NS; q++) pre[q] = base[aoff[q]];
+        for (int q = 0; q < NS; q++) {
+            pre[q] = a.A[po + aoff[q]];
+            preZ[q] = kZ ? a.Z[po + aoff[q]] : T(0);
+        }
     }
 
     for (int j = 0; j < nplanes; j++) {
@@ -173,13 +178,16 @@ __global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
             if (idx < nrc) {
                 int r, c;
                 slot_rc(q, r, c);
-                sU[r * NC + c] = pre[q];
+                sU[r * NC + c] = kZ ? pre[q] + preZ[q] : pre[q];
             }
         }
         if (j + 1 < nplanes) {
-            const T* base = a.A + (int64_t)plane_of(j + 1) * a.av.s[0];
+            const int64_t po = (int64_t)plane_of(j + 1) * a.av.s[0];
 #pragma unroll
-            for (int q = 0; q < NS; q++) pre[q] = base[aoff[q]];
+            for (int q = 0; q < NS; q++) {
+                pre[q] = a.A[po + aoff[q]];
+                if (kZ) preZ[q] = a.Z[po + aoff[q]];
+            }
         }
         lds_barrier();
 
@@ -312,7 +320,8 @@ __global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
 }
 
 // Recomposition of one level step (Sec. II-A, the inverse of the above):
-// coarse nodes take the corrected coarse values W, fine-only nodes c + Pi W.
+// coarse nodes take the corrected coarse values W - Z (Z the correction of
+// this level step), fine-only nodes c + Pi (W - Z).
 // Same tiling and streaming as k_stream_level, over coarse planes: for each
 // coarse plane a the workgroup stages its kT1+1 x kT2+1 coarse tile in LDS,
 // every thread forms the 2-D prolongation Q(a) at its NQ fine nodes (kept in
@@ -393,11 +402,15 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon(StreamArgs<T> a)
     const int64_t as0 = a.av.s[0];
     auto planeA = [=](int f) { return Abase + (int64_t)f * as0; };
 
-    T preW[NW], preC0[NQ], preC1[NQ];
+    // coarse values of this level step: W minus the correction Z (same layout)
+    T preW[NW], preZ[NW], preC0[NQ], preC1[NQ];
     {
-        const T* wb = a.W + (int64_t)P0 * a.wv.s[0];
+        const int64_t wo = (int64_t)P0 * a.wv.s[0];
 #pragma unroll
-        for (int q = 0; q < NW; q++) preW[q] = wb[woff[q]];
+        for (int q = 0; q < NW; q++) {
+            preW[q] = a.W[wo + woff[q]];
+            preZ[q] = a.Z[wo + woff[q]];
+        }
         // coefficients of fine planes 2P0 - 1 (if it belongs to us: never,
         // plane 2P0-1 is the previous chunk's) and 2P0
         const T* cb = planeA(2 * P0);
@@ -417,7 +430,7 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon(StreamArgs<T> a)
 #pragma unroll
         for (int q = 0; q < NW; q++) {
             const int idx = tid + q * kThreads;
-            if (idx < CR * CC) sWb[idx] = preW[q];
+            if (idx < CR * CC) sWb[idx] = preW[q] - preZ[q];
         }
         T cOdd[NQ], cEven[NQ];
 #pragma unroll
@@ -426,9 +439,12 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon(StreamArgs<T> a)
             cEven[q] = preC1[q];
         }
         if (ac + 1 <= A1) {
-            const T* wb = a.W + (int64_t)(ac + 1) * a.wv.s[0];
+            const int64_t wo = (int64_t)(ac + 1) * a.wv.s[0];
 #pragma unroll
-            for (int q = 0; q < NW; q++) preW[q] = wb[woff[q]];
+            for (int q = 0; q < NW; q++) {
+                preW[q] = a.W[wo + woff[q]];
+                preZ[q] = a.Z[wo + woff[q]];
+            }
             const T* co = planeA(2 * ac + 1);
             const T* ce = planeA(min(2 * ac + 2, m0 - 1));
 #pragma unroll
@@ -481,16 +497,18 @@ hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
         const int want = 2048;
         const int nch = (want + tiles - 1) / tiles;
         chunk = (c0 + nch - 1) / nch;
-        if (chunk < 8) chunk = 8;
+        if (chunk < 2) chunk = 2;
         if (chunk > kMaxChunk) chunk = kMaxChunk;
     }
     a.chunk = chunk;
     a.nch = kAct0 ? (c0 + chunk - 1) / chunk : 1;
     const unsigned grid = (unsigned)(tiles * a.nch);
-    if (dec)
-        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    if (dec && a.Z)
+        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, true, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (dec)
+        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, true, false>), dim3(grid), dim3(kThreads), 0, st, a);
     else
-        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, false>), dim3(grid), dim3(kThreads), 0, st, a);
+        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, false, false>), dim3(grid), dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -505,7 +523,7 @@ hipError_t launch_recon_cfg(StreamArgs<T> a, hipStream_t st)
     if (kAct0) {
         const int nch = (2048 + tiles - 1) / tiles;
         chunk = (c0 + nch - 1) / nch;
-        if (chunk < 8) chunk = 8;
+        if (chunk < 2) chunk = 2;
         if (chunk > kMaxChunk) chunk = kMaxChunk;
     }
     a.chunk = chunk;

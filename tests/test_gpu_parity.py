@@ -47,7 +47,21 @@ CASES = [
     ((3, 5, 9), torch.float32, False, 1),
     ((65, 9, 129), torch.float32, False, 3),
     ((17, 17, 17), torch.float64, True, 0),
+    ((1025, 33), torch.float64, True, -1),
+    ((33, 1025), torch.float32, True, -1),
+    ((129, 65, 257), torch.float32, True, -1),
+    ((257, 17, 33), torch.float64, False, -1),
 ]
+
+
+@pytest.fixture(params=["tail", "notail"])
+def tail_mode(request):
+    """Runs a test with the small coarse levels in the combined single-
+    workgroup launch (default) and with every level on the large-level
+    kernels."""
+    prev = mgr.mgr_set_tail_max_nodes(0 if request.param == "notail" else 5000)
+    yield request.param
+    mgr.mgr_set_tail_max_nodes(prev)
 
 
 def case_id(c):
@@ -56,7 +70,7 @@ def case_id(c):
 
 
 @pytest.mark.parametrize("case", CASES, ids=[case_id(c) for c in CASES])
-def test_decompose_matches_oracle(case):
+def test_decompose_matches_oracle(case, tail_mode):
     shape, dt, nu, L = case
     x, xd, coords = field(shape, 100 + len(shape), nu, dt)
     want = oracle.decompose(xd, coords, L)
@@ -67,7 +81,7 @@ def test_decompose_matches_oracle(case):
 
 
 @pytest.mark.parametrize("case", CASES, ids=[case_id(c) for c in CASES])
-def test_recompose_matches_oracle(case):
+def test_recompose_matches_oracle(case, tail_mode):
     shape, dt, nu, L = case
     x, xd, coords = field(shape, 200 + len(shape), nu, dt)
     refac = torch.from_numpy(oracle.decompose(xd, coords, L)).to(dt)
@@ -92,7 +106,7 @@ def test_adjoint_matches_oracle(case):
 
 @pytest.mark.parametrize("shape,dt", [((65, 33, 17), torch.float64), ((129, 65), torch.float32),
                                       ((257,), torch.float64)])
-def test_in_place_equals_out_of_place(shape, dt):
+def test_in_place_equals_out_of_place(shape, dt, tail_mode):
     x, _, coords = field(shape, 7, True, dt)
     xg = x.to(DEV)
     for fn in (mgr.mgr_decompose, mgr.mgr_recompose, mgr.mgr_decompose_adjoint):
