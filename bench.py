@@ -102,27 +102,42 @@ def copy_bandwidth(mgr, torch, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / dt / 1e9  # read + write bytes per second
 
 
-def cpu_baseline():
-    """The CPU oracle (FP64, single thread) on a bounded sample: one 257^3
-    sinusoid-plus-noise field and one 257^3 blob field, each decomposed and
-    recomposed once; reported as the float32 workload's GB/s (4 bytes/node)."""
+def cpu_baseline(u_sin):
+    """The CPU oracle (plain C, FP64, one thread) on one step of the headline
+    workload: the 513^3 sinusoid-plus-noise field (rounded to float32, as the
+    GPU sees it) decomposed and recomposed once.  Rate in the metric's unit:
+    float32 input bytes (4 per node) per direction, as for the GPU."""
     import oracle
-    from paper_2007_04457_amd import synth
 
-    shape = (257, 257, 257)
-    n = int(np.prod(shape))
-    t = 0.0
-    for gen, seed in ((synth.sinusoid_field, SEED_SIN), (synth.blob_field, SEED_BLOB)):
-        u, _ = gen(shape, seed)
-        u = u.astype(np.float32).astype(np.float64)
-        t0 = time.perf_counter()
-        d = oracle.decompose(u)
-        oracle.recompose(d)
-        t += time.perf_counter() - t0
-    gbps = 2 * 2 * n * 4 / t / 1e9
-    return {"value": round(gbps, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "257^3 sinusoid + 257^3 blob fields, FP64 oracle, one decompose+recompose each, "
-                      f"{t:.1f} s; rate counted in float32 input bytes (4 B/node) per direction"}
+    u = u_sin.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    d = oracle.decompose(u)
+    oracle.recompose(d)
+    t = time.perf_counter() - t0
+    n = u.size
+    return {"value": round(2 * n * 4 / t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"one decompose+recompose of the full 513^3 sinusoid field (FP64 oracle, "
+                      f"single thread, {t:.1f} s); GB/s counted as float32 input bytes per direction"}
+
+
+# HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes scaled by the same counters on a copy kernel of known size; valid
+# only while the kernel source matches the one the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_dec_513cube_f32_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_04457_amd", "csrc", "mgr_stream.hip")
+
+
+def measured_traffic():
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha256")))
+    if fields.get("source_sha256", "").strip() != src:
+        return None
+    return int(fields["traffic_bytes"].strip())
 
 
 def main():
@@ -174,7 +189,8 @@ def main():
                 ab = algorithmic_bytes(DOMINANT, SHAPE, s)
                 achieved = ab / (per_launch_ms * 1e-3) / 1e9
                 roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                        "traffic": measured_traffic(),
                         "kernel": DOMINANT, "level": 0, "launch_ms": round(per_launch_ms, 4),
                         "launches": launches, "algorithmic_bytes": ab}
             td, tr = split_times(mgr, torch, x, y, r)
@@ -205,7 +221,7 @@ def main():
     }
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(u_sin)
     print(json.dumps(out), flush=True)
 
 

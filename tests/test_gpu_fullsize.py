@@ -1,0 +1,150 @@
+"""GPU path against the CPU FP64 oracle at the full workload sizes, element
+by element, in the launch configuration the benchmark times (out of place,
+default level count and combined coarse-level launch):
+
+* 513^3 uniform, float32 sinusoid-plus-noise and float64 Gaussian blobs;
+* 8193^2 float64 and 1025x1025x257 float32 on nonuniform coordinates;
+* the 257^3 float32 Gaussian-blob field through the adjoint, and the
+  gradient of the level-weighted loss through the autograd function;
+* the adjoint in float64 against central finite differences of the loss
+  (17^3) and against the explicit dense transposed operator (9^3).
+
+The oracle is single-threaded C; each full-size case costs a few seconds of
+CPU time and a few GiB of host memory.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dense_ref
+import oracle
+import paper_2007_04457_amd as mgr
+from paper_2007_04457_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 2e-5}
+DEV = "cuda:0"
+
+
+def rel_err(got, want, scale):
+    return float(np.max(np.abs(got - want))) / max(scale, 1e-300)
+
+
+FULL = [
+    # shape, dtype, generator, seed, nonuniform
+    ((513, 513, 513), torch.float32, synth.sinusoid_field, 1, False),
+    ((513, 513, 513), torch.float64, synth.blob_field, 2, False),
+    ((8193, 8193), torch.float64, synth.sinusoid_field, 3, True),
+    ((1025, 1025, 257), torch.float32, synth.sinusoid_field, 4, True),
+]
+
+
+def full_id(c):
+    return f"{'x'.join(map(str, c[0]))}-{str(c[1]).split('.')[-1]}-{c[2].__name__}"
+
+
+@pytest.mark.parametrize("case", FULL, ids=[full_id(c) for c in FULL])
+def test_full_size_decompose_recompose(case):
+    shape, dt, gen, seed, nu = case
+    print(f"\n[full] {full_id(case)} seed {seed}", flush=True)
+    u, coords = gen(shape, seed, nonuniform=nu)
+    x = torch.from_numpy(u).to(dt)
+    del u
+    xd = x.double().numpy()
+    scale = float(np.max(np.abs(xd)))
+
+    xg = x.to(DEV)
+    yg = mgr.decompose(xg, coords)
+    torch.cuda.synchronize()
+    got = yg.double().cpu().numpy()
+    want = oracle.decompose(xd, coords)
+    err = rel_err(got, want, scale)
+    assert err <= TOL[dt], ("decompose", err)
+    del got
+
+    # recompose the oracle's refactored array (rounded to the dtype)
+    refac = torch.from_numpy(want).to(dt)
+    del want
+    rd = refac.double().numpy()
+    want_r = oracle.recompose(rd, coords)
+    rg = mgr.recompose(refac.to(DEV), coords)
+    torch.cuda.synchronize()
+    err = rel_err(rg.double().cpu().numpy(), want_r, float(np.max(np.abs(rd))))
+    assert err <= TOL[dt], ("recompose", err)
+
+    # and the GPU round trip returns the input
+    rt = mgr.recompose(yg, coords)
+    torch.cuda.synchronize()
+    err = float((rt - xg).abs().max().item()) / scale
+    assert err <= TOL[dt], ("roundtrip", err)
+
+
+def test_full_size_adjoint_257_blobs():
+    shape = (257, 257, 257)
+    print("\n[full] adjoint 257^3 float32 blobs seed 5", flush=True)
+    u, _ = synth.blob_field(shape, 5)
+    g = torch.from_numpy(u).to(torch.float32)
+    gd = g.double().numpy()
+    want = oracle.decompose_adjoint(gd)
+    a = mgr.decompose_adjoint(g.to(DEV))
+    torch.cuda.synchronize()
+    err = rel_err(a.double().cpu().numpy(), want, max(np.max(np.abs(gd)), np.max(np.abs(want))))
+    assert err <= TOL[torch.float32], err
+
+
+def test_full_size_loss_gradient_257_blobs():
+    """Gradient of sum_l 2^l ||class l||^2 through the autograd function:
+    2 D^T (w * D x), against the oracle applied to the same float32 x."""
+    shape = (257, 257, 257)
+    print("\n[full] loss gradient 257^3 float32 blobs seed 6", flush=True)
+    u, _ = synth.blob_field(shape, 6)
+    x = torch.from_numpy(u).to(torch.float32)
+    xd = x.double().numpy()
+    w = np.power(2.0, oracle.class_map(shape)).astype(np.float32)
+    xg = x.to(DEV).requires_grad_(True)
+    y = mgr.Decompose.apply(xg, None, -1)
+    loss = (torch.from_numpy(w).to(DEV) * y * y).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    want = oracle.decompose_adjoint(2.0 * w.astype(np.float64) * oracle.decompose(xd))
+    err = rel_err(xg.grad.double().cpu().numpy(), want, float(np.max(np.abs(want))))
+    assert err <= 1e-4, err  # two float32 passes and a float32 weighting
+
+
+def test_adjoint_finite_difference_17cubed_gpu():
+    """The loss is quadratic in x, so its float64 central difference along a
+    direction e equals <grad, e> up to rounding."""
+    rng = np.random.default_rng(61)
+    shape = (17, 17, 17)
+    L = mgr.mgr_max_levels(shape)
+    w = torch.from_numpy(np.power(2.0, mgr.mgr_class_map(shape, L))).to(DEV)
+    x = torch.from_numpy(rng.standard_normal(shape)).to(DEV)
+
+    def loss(v):
+        d = mgr.decompose(v, None, L)
+        return float((w * d * d).sum().item())
+
+    xg = x.clone().requires_grad_(True)
+    y = mgr.Decompose.apply(xg, None, L)
+    (w * y * y).sum().backward()
+    for t in range(6):
+        e = torch.from_numpy(rng.standard_normal(shape)).to(DEV)
+        eps = 1e-3
+        fd = (loss(x + eps * e) - loss(x - eps * e)) / (2 * eps)
+        an = float((xg.grad * e).sum().item())
+        assert abs(fd - an) <= 1e-9 * abs(an), (t, fd, an)
+
+
+def test_adjoint_equals_dense_transpose_9cubed_gpu():
+    """D^T g on the GPU (float64) against the transpose of the explicit
+    decomposition matrix assembled from the L2 projections."""
+    rng = np.random.default_rng(62)
+    for shape, nonuni in [((9, 9, 9), False), ((9, 9, 9), True)]:
+        coords = synth.draw_coords(rng, shape) if nonuni else None
+        L = mgr.mgr_max_levels(shape)
+        D = dense_ref.decompose_matrix(shape, coords, L)
+        g = rng.standard_normal(shape)
+        got = mgr.decompose_adjoint(torch.from_numpy(g).to(DEV), coords, L).cpu().numpy()
+        want = (D.T @ g.reshape(-1)).reshape(shape)
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)), shape
