@@ -27,6 +27,16 @@ struct DimTables {
     const T* K[3];
 };
 
+// Two-point interpolation wl*a + wh*b with one fixed rounding order, shared
+// by every kernel that forms the multilinear interpolant, so that different
+// kernels computing the same coefficient agree bit for bit (the compiler
+// would otherwise pick which product to fuse).
+template <typename T>
+__device__ __forceinline__ T lerp2(T wl, T a, T wh, T b)
+{
+    return fma(wh, b, wl * a);
+}
+
 // Arguments of the streaming level kernel (mgr_stream.hip).
 template <typename T>
 struct StreamArgs {

@@ -80,13 +80,13 @@ __device__ __forceinline__ T interp_corners(const T* __restrict__ A, const View3
             int64_t q0 = kHalf ? i0 >> 1 : i0, q1 = kHalf ? i1 >> 1 : i1;
             T vlo = A[at(av, q0, q1, kHalf ? l2 >> 1 : l2)];
             T vhi = (h2 != l2) ? A[at(av, q0, q1, kHalf ? h2 >> 1 : h2)] : T(0);
-            r1[b] = c.wl[2] * vlo + c.wh[2] * vhi;
+            r1[b] = lerp2(c.wl[2], vlo, c.wh[2], vhi);
             if (c.hi[1] == c.lo[1]) { r1[1] = T(0); break; }
         }
-        r0[a] = c.wl[1] * r1[0] + c.wh[1] * r1[1];
+        r0[a] = lerp2(c.wl[1], r1[0], c.wh[1], r1[1]);
         if (c.hi[0] == c.lo[0]) { r0[1] = T(0); break; }
     }
-    return c.wl[0] * r0[0] + c.wh[0] * r0[1];
+    return lerp2(c.wl[0], r0[0], c.wh[0], r0[1]);
 }
 
 // Coefficients (Sec. II-A.1) of one level step: c(p) = u(p) - Pi u(p) at

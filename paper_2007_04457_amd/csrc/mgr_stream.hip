@@ -25,6 +25,9 @@
 //               coarse values W and f.
 // kDec = false: input already holds coefficients at fine-only nodes (values
 //               at coarse positions are ignored); writes f only.
+#include <algorithm>
+#include <type_traits>
+
 #include "mgr_internal.h"
 
 namespace mgr {
@@ -53,31 +56,97 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
     return (x < rem) ? x * (lo + 1) + local : rem * (lo + 1) + (x - rem) * lo + local;
 }
 
-constexpr int kMaxChunk = 64;  // coarse planes per workgroup (LDS tables)
+// Geometry of the streaming level kernel, per problem dimensionality.
+//  3-D: a workgroup owns kT1 = 8 coarse rows x kT2 = 30 coarse columns; its
+//       staged region is 19 fine rows x 64 columns (63 used), one wave per
+//       row (rows r = wave, wave + 4, ...), lane = column.
+//  2-D (m0, 1, m2) and 1-D (1, 1, m2): one staged row of 256 columns (255
+//       used), four waves side by side; kT2 = 126 coarse columns.
+template <bool kAct1>
+struct LevelGeom {
+    static constexpr int kT1 = kAct1 ? 8 : 1;
+    static constexpr int kT2 = kAct1 ? 30 : 126;
+    static constexpr int NR = kAct1 ? 2 * kT1 + 3 : 1;  // staged rows
+    static constexpr int CW = kAct1 ? 1 : 4;            // waves per staged row
+    static constexpr int NCW = 64 * CW;                 // staged columns
+    static constexpr int RW = 4 / CW;                   // rows handled at once
+    static constexpr int NRW = (NR + RW - 1) / RW;      // rows per wave
+    static constexpr int H = NCW / 2;                   // even (odd) columns per row
+    static constexpr int GW = kAct1 ? 32 : 256;         // dim-2 outputs per pass row
+    static constexpr int OB = NR * H + 16;              // odd-column block (bank offset 16)
+    static_assert(2 * kT2 + 3 <= NCW, "region fits the staged width");
+    static_assert(kT2 + 2 <= H && kT2 <= GW, "stencil windows fit");
+};
 
-template <typename T, bool kAct0, bool kAct1, int kT1, int kT2, bool kDec, bool kZ>
+constexpr int kMaxChunk = 128;       // coarse planes per workgroup (LDS tables)
+constexpr unsigned kOut = 0x80000000u;  // buffer offset past every range: loads 0, stores dropped
+
+// Marks a value the same in every lane (kept in scalar registers).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uni(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Raw buffer access (gfx9 descriptor): the hardware range check turns an
+// offset at or past `bytes` into a load of zero or a dropped store.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes)
+{
+    // base and size are wave-uniform; say so, or the compiler loops over lanes
+    const unsigned long long b = (unsigned long long)base;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    void* ub = (void*)(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, __builtin_amdgcn_readfirstlane((int)bytes), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ>
 __global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
 {
-    static_assert(kT1 * kT2 == kThreads, "one coarse column per thread");
-    constexpr int NR = kAct1 ? 2 * kT1 + 3 : 1;
-    constexpr int NC = 2 * kT2 + 3;
-    constexpr int NS = (NR * NC + kThreads - 1) / kThreads;   // region slots per thread
-    constexpr int NG = (NR * kT2 + kThreads - 1) / kThreads;  // dim-2 outputs per thread
-    constexpr int NF = kAct0 ? 2 * kMaxChunk + 3 : 1;         // staged fine planes
-    __shared__ T sU[NR * NC];
-    __shared__ T sP[kDec ? 2 * NR * NC : 1];
-    __shared__ T sG[NR * kT2];
-    // Every table the plane loop needs lives in LDS: a global load inside the
-    // loop would have to wait for the next plane's prefetch (vector memory
-    // counters retire in order).
-    __shared__ T sWr[2 * NR];        // row interpolation weights (lower, upper)
-    __shared__ T sWc[2 * NC];        // column interpolation weights
-    __shared__ T sW0[2 * NF];        // plane interpolation weights
-    __shared__ T sK2[5 * kT2];       // dim-2 stencil of the tile's coarse columns
-    __shared__ T sK1[5 * kT1];       // dim-1 stencil of the tile's coarse rows
-    __shared__ T sK0[5 * kMaxChunk]; // dim-0 stencil of the chunk's coarse planes
+    using G = LevelGeom<kAct1>;
+    constexpr int NR = G::NR, NCW = G::NCW, NRW = G::NRW, RW = G::RW, H = G::H, GW = G::GW;
+    constexpr int kT1 = G::kT1, kT2 = G::kT2, OB = G::OB;
+    constexpr int NGP = (NR + (kThreads / GW) - 1) / (kThreads / GW);  // dim-2 passes
+    constexpr unsigned S = sizeof(T);
+    // sU: the staged plane (even planes); sC: coefficients (zero at coarse
+    // and outside nodes), even columns [r][H] then odd columns, so that the
+    // dim-2 stencil reads consecutive words; sG: dim-2 results [r][GW].
+    __shared__ T sU[kDec ? NR * NCW : 1];
+    __shared__ T sC[OB + NR * H];
+    __shared__ T sG[NR * GW];
+    __shared__ T sW0[kDec && kAct0 ? 2 * (2 * kMaxChunk + 3) : 1];  // plane interpolation weights
+    __shared__ T sK0[kAct0 ? 5 * (kMaxChunk + 3) : 1];            // dim-0 stencil, planes P0-1 .. P1+1
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = uni(tid >> 6);
     const int bid = remap_xcd((int)blockIdx.x, (int)gridDim.x);
     const int nt1 = a.nt1, nt2 = a.nt2;
     const int t2 = bid % nt2;
@@ -86,237 +155,266 @@ __global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
 
     const int m0 = (int)a.av.n[0], m1 = (int)a.av.n[1], m2 = (int)a.av.n[2];
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
-    // in-plane strides fit 32 bits (the driver keeps planes below 2^31 nodes)
+    const int I1 = t1 * kT1, I2 = t2 * kT2;
+    const int P0 = ch * a.chunk, P1 = min(P0 + a.chunk, c0);
+    const int R0 = kAct1 ? 2 * I1 - 2 : 0;  // region origin (may be negative)
+    const int C0 = 2 * I2 - 2;
+    const int RB = max(R0, 0);              // first in-grid region row
+    const int F0 = kAct0 ? max(2 * P0 - 2, 0) : 0;
+    const int F1 = kAct0 ? min(2 * P1, m0 - 1) : 0;
+    const int oF0 = kAct0 ? 2 * P0 : 0, oF1 = kAct0 ? min(2 * P1, m0) : 1;
+
+    if (kDec && kAct0)
+        for (int e = tid; e < 2 * (F1 - F0 + 1); e += kThreads) sW0[e] = a.tb.w[0][2 * F0 + e];
+    if (kAct0)
+        // rows P0-1 .. P1+1, zero outside [P0, P1): no plane of another chunk
+        // receives contributions from this one
+        for (int e = tid; e < 5 * (P1 - P0 + 3); e += kThreads) {
+            const int i = P0 - 1 + e / 5;
+            sK0[e] = (i >= P0 && i < P1) ? a.tb.K[0][5 * i + e % 5] : T(0);
+        }
+
+    // ---- this lane's staged column
+    const int c = (wave % G::CW) * 64 + lane;
+    const int gc = C0 + c;
+    const bool cin = c < 2 * kT2 + 3 && gc >= 0 && gc < m2;
+    const bool cown = cin && gc >= 2 * I2 && gc < min(2 * (I2 + kT2), m2);
+    const bool ceven = !(c & 1);
+    // interpolation weights: zero outside the grid, so outside nodes get a
+    // zero coefficient (their loads return zero); (1, 0) at even columns, so
+    // coarse nodes get exactly u - u = 0
+    T wcl = T(0), wch = T(0);
+    int ucl = 0, ucr = 0;
+    if (kDec && cin) {
+        ucl = c & ~1;
+        ucr = ucl + 2 * (c & 1);
+        wcl = (c & 1) ? a.tb.w[2][2 * gc] : T(1);
+        wch = (c & 1) ? a.tb.w[2][2 * gc + 1] : T(0);
+    }
+    // ---- this wave's staged rows r = rg + RW * k (wave-uniform)
+    const int rg = wave / G::CW;
+    T* const sUw = sU + rg * NCW + c;
+    const T* const sUl = sU + rg * NCW + ucl;
+    const T* const sUr = sU + rg * NCW + ucr;
+    T* const sCw = sC + rg * H + (c & 1) * OB + (c >> 1);
     const int as1 = (int)a.av.s[1], as2 = (int)a.av.s[2];
     const int cs1 = (int)a.cv.s[1], cs2 = (int)a.cv.s[2];
     const int ws1 = (int)a.wv.s[1], ws2 = (int)a.wv.s[2];
-    const int fs1 = (int)a.fv.s[1], fs2 = (int)a.fv.s[2];
-
-    const int I1 = t1 * kT1, I2 = t2 * kT2;
-    const int P0 = ch * a.chunk, P1 = min(P0 + a.chunk, c0);
-    // staged fine region (starts and ends on even indices)
-    const int R0 = kAct1 ? max(2 * I1 - 2, 0) : 0;
-    const int R1 = kAct1 ? min(2 * (min(I1 + kT1, c1) - 1) + 2, m1 - 1) : 0;
-    const int C0 = max(2 * I2 - 2, 0);
-    const int C1 = min(2 * (min(I2 + kT2, c2) - 1) + 2, m2 - 1);
-    const int nr = R1 - R0 + 1, nc = C1 - C0 + 1, nrc = nr * nc;
-    const int F0 = kAct0 ? max(2 * P0 - 2, 0) : 0;
-    const int F1 = kAct0 ? min(2 * (P1 - 1) + 2, m0 - 1) : 0;
-    // fine nodes this workgroup writes: rows [oR0, oR1), cols [oC0, oC1), planes [oF0, oF1)
     const int oR0 = kAct1 ? 2 * I1 : 0, oR1 = kAct1 ? min(2 * (I1 + kT1), m1) : 1;
-    const int oC0 = 2 * I2, oC1 = min(2 * (I2 + kT2), m2);
-    const int oF0 = kAct0 ? 2 * P0 : 0, oF1 = kAct0 ? min(2 * P1, m0) : 1;
-    const float inv_nc = 1.0f / (float)nc;
-
-    // ---- tables -> LDS
-    if (kDec) {
-        const T* __restrict__ w1 = a.tb.w[1];
-        const T* __restrict__ w2 = a.tb.w[2];
-        for (int r = tid; r < nr; r += kThreads) {
-            const int gr = R0 + r;
-            sWr[2 * r] = (gr & 1) ? w1[2 * gr] : T(1);
-            sWr[2 * r + 1] = (gr & 1) ? w1[2 * gr + 1] : T(0);
+    unsigned vA[NRW], vC[NRW], vW[NRW];  // byte offsets from the region's first in-grid row
+    T wrl[NRW], wrh[NRW];
+#pragma unroll
+    for (int k = 0; k < NRW; k++) {
+        const int r = rg + RW * k;
+        const int gr = R0 + r;
+        const bool rin = r < NR && gr >= 0 && gr < m1;
+        const bool own = rin && cown && gr >= oR0 && gr < oR1;
+        vA[k] = (rin && cin) ? (unsigned)((gr - RB) * as1 + gc * as2) * S : kOut;
+        vC[k] = own ? (unsigned)((gr - RB) * cs1 + gc * cs2) * S : kOut;
+        vW[k] = (own && !(gr & 1) && ceven) ? (unsigned)(((gr - RB) >> 1) * ws1 + (gc >> 1) * ws2) * S : kOut;
+        wrl[k] = T(0);
+        wrh[k] = T(0);
+        if (kDec && rin) {
+            wrl[k] = (kAct1 && (r & 1)) ? uni(a.tb.w[1][2 * gr]) : T(1);
+            wrh[k] = (kAct1 && (r & 1)) ? uni(a.tb.w[1][2 * gr + 1]) : T(0);
         }
-        for (int c = tid; c < nc; c += kThreads) {
-            const int gc = C0 + c;
-            sWc[2 * c] = (gc & 1) ? w2[2 * gc] : T(1);
-            sWc[2 * c + 1] = (gc & 1) ? w2[2 * gc + 1] : T(0);
-        }
-        if (kAct0)
-            for (int e = tid; e < 2 * (F1 - F0 + 1); e += kThreads) sW0[e] = a.tb.w[0][2 * F0 + e];
     }
-    for (int e = tid; e < 5 * kT2; e += kThreads) sK2[e] = (I2 + e / 5 < c2) ? a.tb.K[2][5 * I2 + e] : T(0);
-    if (kAct1)
-        for (int e = tid; e < 5 * kT1; e += kThreads) sK1[e] = (I1 + e / 5 < c1) ? a.tb.K[1][5 * I1 + e] : T(0);
-    if (kAct0)
-        for (int e = tid; e < 5 * (P1 - P0); e += kThreads) sK0[e] = a.tb.K[0][5 * P0 + e];
+    // bytes reachable from the region's first in-grid row, per array
+    const unsigned spanA = (unsigned)((min(R0 + NR, m1) - RB) * as1 + m2 * as2) * S;
+    const unsigned spanC = (unsigned)((min(R0 + NR, m1) - RB) * cs1 + m2 * cs2) * S;
+    const unsigned spanW = (unsigned)(((min(R0 + NR, m1) - RB) / 2 + 1) * ws1 + ((m2 + 1) / 2) * ws2) * S;
 
-    // ---- this thread's coarse column of the output tile
-    const int g1 = tid / kT2, g2 = tid % kT2;
-    const int i1 = I1 + g1, i2 = I2 + g2;
-    const bool gvalid = (i1 < c1) && (i2 < c2);
-    const int foff = i1 * fs1 + i2 * fs2;
-    T acc0 = T(0), acc1 = T(0), acc2 = T(0);
+    // ---- dim-2 / dim-1 stencil weights of this thread's output column
+    const int g2 = tid % GW, g1 = tid / GW;  // output: coarse row I1+g1, column I2+g2
+    T k2[5], k1[5];
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+        k2[t] = (g2 < kT2 && I2 + g2 < c2) ? a.tb.K[2][5 * (I2 + g2) + t] : T(0);
+        k1[t] = (kAct1 && g1 < kT1 && I1 + g1 < c1) ? a.tb.K[1][5 * (I1 + g1) + t] : T(0);
+    }
+    const bool gvalid = g1 < kT1 && g2 < kT2 && I1 + g1 < c1 && I2 + g2 < c2;
+    const unsigned vF = gvalid ? (unsigned)((I1 + g1) * (int)a.fv.s[1] + (I2 + g2) * (int)a.fv.s[2]) * S : kOut;
+    const unsigned spanF = (unsigned)((c1 - 1) * (int)a.fv.s[1] + c2 * (int)a.fv.s[2]) * S;
 
-    const int nplanes = F1 - F0 + 1;
-    auto plane_of = [=](int j) { return (j == 0) ? F0 : ((j & 1) ? F0 + j + 1 : F0 + j - 1); };
-    // slot q of this thread covers region node tid + q * kThreads; idle slots
-    // re-load the region's first node so that every load is unconditional
-    auto slot_rc = [=](int q, int& r, int& c) {
-        const int idx = tid + q * kThreads;
-        r = (int)(((float)idx + 0.5f) * inv_nc);
-        c = idx - r * nc;
-        return idx < nrc;
+    // plane strides are below 2^31 (checked by the launcher): 32 x 32 -> 64 products
+    const unsigned as0 = (unsigned)a.av.s[0], cs0 = (unsigned)a.cv.s[0], ws0 = (unsigned)a.wv.s[0],
+                   fs0 = (unsigned)a.fv.s[0];
+    auto mul64 = [](int i, unsigned st) { return (int64_t)((uint64_t)(unsigned)i * st); };
+    // all loads are unconditional: a load under a branch makes the compiler
+    // wait for every outstanding load where the paths join
+    auto load_plane = [&](int f, T (&v)[NRW], T (&vz)[NRW]) {
+        const int64_t po = mul64(f, as0) + (int64_t)RB * as1;
+        const __amdgpu_buffer_rsrc_t rA = make_rsrc(a.A + po, spanA);
+        const __amdgpu_buffer_rsrc_t rZ = make_rsrc(kZ ? a.Z + po : a.A, spanA);
+#pragma unroll
+        for (int k = 0; k < NRW; k++) {
+            v[k] = buf_load<T>(rA, vA[k]);
+            if (kZ) vz[k] = buf_load<T>(rZ, vA[k]);
+        }
     };
-    int aoff[NS];
-#pragma unroll
-    for (int q = 0; q < NS; q++) {
-        int r, c;
-        const bool ok = slot_rc(q, r, c);
-        aoff[q] = ok ? (R0 + r) * as1 + (C0 + c) * as2 : R0 * as1 + C0 * as2;
-    }
 
-    // kZ: the input level grid is A + Z (coarse values plus the correction
-    // of the previous level step, added here instead of in a separate pass)
-    T pre[NS], preZ[NS];
-    {
-        const int64_t po = (int64_t)plane_of(0) * a.av.s[0];
+    // The loop body is specialised on the parity RP of this wave's rows
+    // (rows rg, rg + RW, ... all share it), so per-row branches are static.
+    auto run = [&](auto rpc) {
+    constexpr bool RP = decltype(rpc)::value;
+    // row k of this wave exists (the last one may fall past the region)
+    auto row_exists = [&](int k) {
+        constexpr int rgmax = RP ? ((RW - 1) % 2 ? RW - 1 : RW - 2) : ((RW - 1) % 2 ? RW - 2 : RW - 1);
+        return (rgmax + RW * k < NR) || (rg + RW * k < NR);
+    };
+    // Coefficients of plane f into sC (and C, W); returns through P the 2-D
+    // interpolant of an even plane.  Ends with a barrier after the sC writes.
+    auto coef_plane = [&](int f, bool even, const T (&cur)[NRW], T (&P)[NRW], const T (&Pa)[NRW],
+                          const T (&Pb)[NRW]) {
+        if (!kDec) {
 #pragma unroll
-        for (int q = 0; q < NS; q++) {
-            pre[q] = a.A[po + aoff[q]];
-            preZ[q] = kZ ? a.Z[po + aoff[q]] : T(0);
-        }
-    }
-
-    for (int j = 0; j < nplanes; j++) {
-        const int f = plane_of(j);
-        const bool even = (f & 1) == 0;
-        // stage the prefetched plane, then start loading the next one
-#pragma unroll
-        for (int q = 0; q < NS; q++) {
-            const int idx = tid + q * kThreads;
-            if (idx < nrc) {
-                int r, c;
-                slot_rc(q, r, c);
-                sU[r * NC + c] = kZ ? pre[q] + preZ[q] : pre[q];
-            }
-        }
-        if (j + 1 < nplanes) {
-            const int64_t po = (int64_t)plane_of(j + 1) * a.av.s[0];
-#pragma unroll
-            for (int q = 0; q < NS; q++) {
-                pre[q] = a.A[po + aoff[q]];
-                if (kZ) preZ[q] = a.Z[po + aoff[q]];
-            }
-        }
-        lds_barrier();
-
-        if (kDec) {
-            const bool fown = f >= oF0 && f < oF1;
-            T* __restrict__ Cp = a.C + (int64_t)f * a.cv.s[0];
-            if (even) {
-                // 2-D interpolant P from the plane's coarse nodes, kept for the
-                // odd neighbours; C = u - P in place at fine positions (other
-                // threads read only coarse positions, which stay u).
-                T* P = sP + (((f - F0) >> 1) & 1) * (NR * NC);
-                T* __restrict__ Wp = a.W + (int64_t)(f >> 1) * a.wv.s[0];
-#pragma unroll 1
-                for (int idx = tid; idx < nrc; idx += kThreads) {
-                    const int r = (int)(((float)idx + 0.5f) * inv_nc), c = idx - r * nc;
-                    const int r0 = r - (r & 1), r1 = r + (r & 1);
-                    const int cl = c - (c & 1), cr = c + (c & 1);
-                    const T wcl = sWc[2 * c], wch = sWc[2 * c + 1];
-                    const T lo = wcl * sU[r0 * NC + cl] + wch * sU[r0 * NC + cr];
-                    const T hi = wcl * sU[r1 * NC + cl] + wch * sU[r1 * NC + cr];
-                    const T p = sWr[2 * r] * lo + sWr[2 * r + 1] * hi;
-                    const T u = sU[r * NC + c];
-                    P[r * NC + c] = p;
-                    const bool coarse = !((r | c) & 1);
-                    const T cv = u - p;
-                    if (!coarse) sU[r * NC + c] = cv;
-                    const int gr = R0 + r, gc = C0 + c;
-                    if (fown && gr >= oR0 && gr < oR1 && gc >= oC0 && gc < oC1) {
-                        if (!coarse || a.write_coarse) Cp[gr * cs1 + gc * cs2] = coarse ? u : cv;
-                        if (coarse) Wp[(gr >> 1) * ws1 + (gc >> 1) * ws2] = u;
-                    }
-                }
-            } else {
-                // odd plane: every node is fine; interpolate along dim 0
-                // between the 2-D interpolants of the even neighbours
-                const T* Pa = sP + (((f - 1 - F0) >> 1) & 1) * (NR * NC);
-                const T* Pb = sP + (((f + 1 - F0) >> 1) & 1) * (NR * NC);
-                const T wl = sW0[2 * (f - F0)], wh = sW0[2 * (f - F0) + 1];
-#pragma unroll 1
-                for (int idx = tid; idx < nrc; idx += kThreads) {
-                    const int r = (int)(((float)idx + 0.5f) * inv_nc), c = idx - r * nc;
-                    const int qq = r * NC + c;
-                    const T cv = sU[qq] - (wl * Pa[qq] + wh * Pb[qq]);
-                    sU[qq] = cv;
-                    const int gr = R0 + r, gc = C0 + c;
-                    if (fown && gr >= oR0 && gr < oR1 && gc >= oC0 && gc < oC1) Cp[gr * cs1 + gc * cs2] = cv;
-                }
+            for (int k = 0; k < NRW; k++) {
+                if (!row_exists(k)) continue;
+                // coarse positions hold other classes: read them as zero
+                sCw[RW * k * H] = (even && !RP && ceven) ? T(0) : cur[k];
             }
             lds_barrier();
+            return;
         }
-
-        // dim-2 stencil on every staged row; coarse positions of even planes read 0
+        const bool fown = f >= oF0 && f < oF1;
+        const __amdgpu_buffer_rsrc_t rC = make_rsrc(a.C + mul64(f, cs0) + (int64_t)RB * cs1, fown ? spanC : 0u);
+        if (even) {
+            const __amdgpu_buffer_rsrc_t rW =
+                make_rsrc(a.W + mul64(f >> 1, ws0) + (int64_t)(RB >> 1) * ws1, fown ? spanW : 0u);
 #pragma unroll
-        for (int q = 0; q < NG; q++) {
-            const int idx = tid + q * kThreads;
-            if (idx >= nr * kT2) continue;
-            const int r = idx / kT2, g = idx % kT2;
-            const int ii = I2 + g;
-            T s = T(0);
-            if (ii < c2) {
-                const bool maskrow = even && !(r & 1);
+            for (int k = 0; k < NRW; k++)
+                if (row_exists(k)) sUw[RW * k * NCW] = cur[k];
+            lds_barrier();
 #pragma unroll
-                for (int t = -2; t <= 2; t++) {
-                    const int gc = 2 * ii + t;
-                    if (gc < 0 || gc >= m2) continue;
-                    T v = sU[r * NC + gc - C0];
-                    if (maskrow && !(t & 1)) v = T(0);
-                    s += sK2[5 * g + t + 2] * v;
+            for (int k = 0; k < NRW; k++) {
+                if (!row_exists(k)) continue;
+                T p;
+                if (RP) {
+                    const T lo = lerp2(wcl, sUl[(RW * k - 1) * NCW], wch, sUr[(RW * k - 1) * NCW]);
+                    const T hi = lerp2(wcl, sUl[(RW * k + 1) * NCW], wch, sUr[(RW * k + 1) * NCW]);
+                    p = lerp2(wrl[k], lo, wrh[k], hi);
+                } else {
+                    p = wrl[k] * lerp2(wcl, sUl[RW * k * NCW], wch, sUr[RW * k * NCW]);
                 }
+                P[k] = p;
+                const T cv = cur[k] - p;  // 0 at coarse and outside nodes
+                sCw[RW * k * H] = cv;
+                // coarse positions take u: the output of the finest step
+                // needs it, deeper steps' values there are overwritten later
+                buf_store((!RP && ceven) ? cur[k] : cv, rC, vC[k]);
+                if (!RP) buf_store(cur[k], rW, vW[k]);
             }
-            sG[r * kT2 + g] = s;
+        } else {
+            // odd plane: every node is fine; interpolate along dim 0 between
+            // the 2-D interpolants of the even neighbours
+            const T wl = sW0[2 * (f - F0)], wh = sW0[2 * (f - F0) + 1];
+#pragma unroll
+            for (int k = 0; k < NRW; k++) {
+                if (!row_exists(k)) continue;
+                const T cv = cur[k] - lerp2(wl, Pa[k], wh, Pb[k]);
+                sCw[RW * k * H] = cv;
+                buf_store(cv, rC, vC[k]);
+            }
         }
         lds_barrier();
+    };
 
-        // dim-1 stencil for this thread's column, then the dim-0 stencil into
-        // the running sums of the coarse planes that fine plane f touches
-        if (gvalid) {
-            T g;
-            if (kAct1) {
-                g = T(0);
+    // dim-2 then dim-1 stencils of the plane in sC: this thread's value of
+    // the plane's contribution (zeros stand in for coarse and outside nodes,
+    // so there are no masks or bounds)
+    auto reduce_plane = [&]() -> T {
 #pragma unroll
-                for (int t = -2; t <= 2; t++) {
-                    const int gr = 2 * i1 + t;
-                    if (gr < 0 || gr >= m1) continue;
-                    g += sK1[5 * g1 + t + 2] * sG[(gr - R0) * kT2 + g2];
-                }
-            } else {
-                g = sG[g2];
-            }
-            if (kAct0) {
-                const int ilo = (f - 1) >> 1;  // first coarse plane with |f - 2i| <= 2
-#pragma unroll
-                for (int r = 0; r < 3; r++) {
-                    const int i = ilo + r;
-                    const int t = f - 2 * i;
-                    if (t < -2 || t > 2 || i < P0 || i >= P1) continue;
-                    const T add = sK0[5 * (i - P0) + t + 2] * g;
-                    const int qs = i % 3;
-                    acc0 += (qs == 0) ? add : T(0);
-                    acc1 += (qs == 1) ? add : T(0);
-                    acc2 += (qs == 2) ? add : T(0);
-                }
-                if (!even) {
-                    // both neighbours of coarse plane i = (f-1)/2 are done
-                    const int i = (f - 1) >> 1;
-                    if (i >= P0 && i < P1) {
-                        const int qs = i % 3;
-                        const T v = (qs == 0) ? acc0 : (qs == 1) ? acc1 : acc2;
-                        a.F[(int64_t)i * a.fv.s[0] + foff] = v;
-                        acc0 = (qs == 0) ? T(0) : acc0;
-                        acc1 = (qs == 1) ? T(0) : acc1;
-                        acc2 = (qs == 2) ? T(0) : acc2;
-                    }
-                }
-            } else {
-                a.F[foff] = g;
-            }
+        for (int ps = 0; ps < NGP; ps++) {
+            const int r = g1 + ps * (kThreads / GW);
+            if (NR % (kThreads / GW) != 0 && r >= NR) continue;
+            const T* E = sC + r * H + g2;
+            const T* O = sC + OB + r * H + g2;
+            if (g2 < kT2)
+                sG[r * GW + g2] = k2[0] * E[0] + k2[1] * O[0] + k2[2] * E[1] + k2[3] * O[1] + k2[4] * E[2];
         }
-        // sU is rewritten by the next iteration only after this barrier
         lds_barrier();
-    }
-    if (kAct0 && gvalid && F1 == m0 - 1) {
-        // last coarse plane of the grid: its stencil has no right half
-        const int i = F1 / 2;
-        if (i >= P0 && i < P1) {
-            const int qs = i % 3;
-            a.F[(int64_t)i * a.fv.s[0] + foff] = (qs == 0) ? acc0 : (qs == 1) ? acc1 : acc2;
+        if (kAct1) {
+            const T* Gp = sG + 2 * g1 * GW + g2;
+            return k1[0] * Gp[0] + k1[1] * Gp[GW] + k1[2] * Gp[2 * GW] + k1[3] * Gp[3 * GW] +
+                   k1[4] * Gp[4 * GW];
         }
+        return sG[g2];
+    };
+    // The next plane writes sU and sC only before its first barrier and sG
+    // only after it; every reader of sC passed the dim-2 barrier and every
+    // reader of sG reaches the next plane's first barrier only after reading.
+    auto store_f = [&](int i, T v) { buf_store(v, make_rsrc(a.F + mul64(i, fs0), spanF), vF); };
+
+    T X[NRW], XZ[NRW], Y[NRW], YZ[NRW], cur[NRW], Pp[NRW], Pn[NRW];
+#pragma unroll
+    for (int k = 0; k < NRW; k++) {
+        X[k] = XZ[k] = Y[k] = YZ[k] = Pp[k] = Pn[k] = T(0);
     }
+    lds_barrier();  // tables
+
+    if (!kAct0) {
+        load_plane(0, X, XZ);
+#pragma unroll
+        for (int k = 0; k < NRW; k++) cur[k] = kZ ? X[k] + XZ[k] : X[k];
+        coef_plane(0, true, cur, Pn, Pp, Pp);
+        store_f(0, reduce_plane());
+        return;
+    }
+
+    // Planes in the order F0, then pairs (F0+2k+2, F0+2k+1): an odd plane
+    // follows both even neighbours.  Two planes are in flight: X holds the
+    // odd planes, Y the even ones (planes past F1 re-read F1).  Each buffer
+    // is reloaded right after its last use, so no loaded register is copied
+    // (a copy would wait for the load).
+    const int K = (F1 - F0) / 2;
+    load_plane(F0, X, XZ);
+    load_plane(min(F0 + 2, F1), Y, YZ);
+    // running dim-0 sums of coarse planes A = F0/2 + k, B = A + 1, Cc = A + 2
+    T accA = T(0), accB = T(0), accC = T(0);
+    const T* const k0 = sK0 + 5 * (F0 / 2 - P0 + 1) + 2;  // k0[5 (i - F0/2) + t]
+    auto consume = [&](int f, bool even, T (&B)[NRW], T (&BZ)[NRW], int fnext) {
+        if (kZ) {
+#pragma unroll
+            for (int q = 0; q < NRW; q++) cur[q] = B[q] + BZ[q];
+            load_plane(fnext, B, BZ);
+            coef_plane(f, even, cur, Pn, Pp, Pn);
+        } else {
+            coef_plane(f, even, B, Pn, Pp, Pn);
+            load_plane(fnext, B, BZ);
+        }
+    };
+    consume(F0, true, X, XZ, min(F0 + 1, F1));
+    {
+        const T g = reduce_plane();
+        accA += k0[0] * g;
+        accB += k0[5 - 2] * g;
+    }
+    for (int k = 0; k < K; k++) {
+        const T* const kk = k0 + 5 * k;  // coarse plane ia = F0/2 + k completes in this step
+#pragma unroll
+        for (int q = 0; q < NRW; q++) Pp[q] = Pn[q];
+        consume(F0 + 2 * k + 2, true, Y, YZ, min(F0 + 2 * k + 4, F1));
+        T g = reduce_plane();
+        accA += kk[2] * g;
+        accB += kk[5] * g;
+        accC += kk[10 - 2] * g;
+        consume(F0 + 2 * k + 1, false, X, XZ, min(F0 + 2 * k + 3, F1));
+        g = reduce_plane();
+        accA += kk[1] * g;
+        accB += kk[5 - 1] * g;
+        const int ia = F0 / 2 + k;
+        if (ia >= P0) store_f(ia, accA);
+        accA = accB;
+        accB = accC;
+        accC = T(0);
+    }
+    // last coarse plane of the grid: its stencil has no right half
+    if (F1 == m0 - 1 && F1 / 2 < P1) store_f(F1 / 2, accA);
+    };
+    if (kAct1 && (rg & 1))
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 }
 
 // Recomposition of one level step (Sec. II-A, the inverse of the above):
@@ -483,33 +581,63 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon(StreamArgs<T> a)
     }
 }
 
-template <typename T, bool kAct0, bool kAct1, int kT1, int kT2>
-hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
+// Compute units of the current device (cached per device).
+int cu_count()
 {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+// Workgroups of `kern` that one compute unit holds at once (cached per kernel).
+template <typename K>
+int resident_per_cu(K kern, int& cache)
+{
+    if (cache == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kThreads, 0) != hipSuccess || n <= 0) n = 2;
+        cache = n;
+    }
+    return cache;
+}
+
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ>
+hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st)
+{
+    using G = LevelGeom<kAct1>;
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
-    a.nt1 = kAct1 ? (c1 + kT1 - 1) / kT1 : 1;
-    a.nt2 = (c2 + kT2 - 1) / kT2;
+    a.nt1 = kAct1 ? (c1 + G::kT1 - 1) / G::kT1 : 1;
+    a.nt2 = (c2 + G::kT2 - 1) / G::kT2;
     const int tiles = a.nt1 * a.nt2;
+    auto kern = k_stream_level<T, kAct0, kAct1, kDec, kZ>;
     int chunk = c0;
     if (kAct0) {
-        // enough workgroups to fill 256 CUs several times over, but at least
-        // 8 coarse planes per chunk to keep the 2-plane halo cheap
-        const int want = 2048;
-        const int nch = (want + tiles - 1) / tiles;
+        // One round of resident workgroups: a second, partial round would
+        // run latency-bound on a mostly idle chip.
+        static int occ = 0;
+        const int slots = resident_per_cu(kern, occ) * cu_count();
+        const int nch = std::max(1, slots / tiles);
         chunk = (c0 + nch - 1) / nch;
-        if (chunk < 2) chunk = 2;
-        if (chunk > kMaxChunk) chunk = kMaxChunk;
+        chunk = std::min(std::max(chunk, 2), kMaxChunk);
     }
     a.chunk = chunk;
     a.nch = kAct0 ? (c0 + chunk - 1) / chunk : 1;
-    const unsigned grid = (unsigned)(tiles * a.nch);
-    if (dec && a.Z)
-        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, true, true>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (dec)
-        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, true, false>), dim3(grid), dim3(kThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kT1, kT2, false, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * a.nch)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
+}
+
+template <typename T, bool kAct0, bool kAct1>
+hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
+{
+    if (dec && a.Z) return launch_level_cfg<T, kAct0, kAct1, true, true>(a, st);
+    if (dec) return launch_level_cfg<T, kAct0, kAct1, true, false>(a, st);
+    return launch_level_cfg<T, kAct0, kAct1, false, false>(a, st);
 }
 
 template <typename T, bool kAct0, bool kAct1, int kT1, int kT2>
@@ -551,9 +679,9 @@ template <typename T>
 hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st)
 {
     const bool act0 = a.av.n[0] > 1, act1 = a.av.n[1] > 1;
-    if (act0 && act1) return launch_cfg<T, true, true, 8, 32>(a, dec, st);
-    if (act0) return launch_cfg<T, true, false, 1, 256>(a, dec, st);
-    if (!act1) return launch_cfg<T, false, false, 1, 256>(a, dec, st);
+    if (act0 && act1) return launch_cfg<T, true, true>(a, dec, st);
+    if (act0) return launch_cfg<T, true, false>(a, dec, st);
+    if (!act1) return launch_cfg<T, false, false>(a, dec, st);
     return hipErrorInvalidValue;  // (1, m1, m2) is never formed by the driver
 }
 
