@@ -102,6 +102,84 @@ def copy_bandwidth(mgr, torch, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / dt / 1e9  # read + write bytes per second
 
 
+def event_ms(torch, fn, reps=5, warmup=2):
+    """Median milliseconds of fn() on the current stream (HIP events)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out))
+
+
+def batched_vs_serial(mgr, torch, synth):
+    """The 96-field float32 workload: the batched launches (eager and as a
+    replayed HIP graph, after autotuning) against 96 serial mgr_decompose
+    calls on the same stream."""
+    shapes = [s for s, _ in synth.batched_shapes()]
+    xs = [torch.from_numpy(synth.batched_field(i)).to(torch.float32).cuda() for i in range(len(shapes))]
+    ys = [torch.empty_like(x) for x in xs]
+    nbytes = sum(x.numel() * 4 for x in xs)
+    for x in xs:
+        mgr.mgr_prepare(torch.float32, tuple(x.shape))
+
+    def serial():
+        for x, y in zip(xs, ys):
+            mgr.mgr_decompose(x, y)
+
+    t_serial = event_ms(torch, serial)
+    plan = mgr.BatchPlan(shapes, torch.float32)
+    chunk, launches, items = plan.autotune(xs, ys, top_k=3)
+    t_batch = event_ms(torch, lambda: plan.decompose(xs, ys))
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            plan.decompose(xs, ys)
+    t_graph = event_ms(torch, g.replay)
+    ok = all(torch.equal(y, mgr.decompose(x)) for x, y in zip(xs, ys))
+    del g
+    plan.close()
+    return {"fields": len(xs), "input_bytes": nbytes, "serial_ms": round(t_serial, 4),
+            "batched_ms": round(t_batch, 4), "graph_ms": round(t_graph, 4),
+            "serial_GBps": round(nbytes / t_serial / 1e6, 2), "graph_GBps": round(nbytes / t_graph / 1e6, 2),
+            "speedup_vs_serial": round(t_serial / t_graph, 3), "chunk": chunk, "launches": launches,
+            "items": items, "matches_serial_bitwise": bool(ok)}
+
+
+def adjoint_timing(mgr, torch, synth, oracle_free=True):
+    """257^3 float32 Gaussian-blob field through the autograd function with
+    the level-weighted loss sum_l 2^l ||class l||^2: forward + backward
+    against the plain decomposition, and the adjoint alone."""
+    shape = (257, 257, 257)
+    u, _ = synth.blob_field(shape, 5)
+    x = torch.from_numpy(u).to(torch.float32).cuda()
+    w = torch.from_numpy(np.power(2.0, mgr.mgr_class_map(shape)).astype(np.float32)).cuda()
+    y = torch.empty_like(x)
+    g = torch.empty_like(x)
+    mgr.mgr_prepare(torch.float32, shape)
+    t_dec = event_ms(torch, lambda: mgr.mgr_decompose(x, y))
+    t_adj = event_ms(torch, lambda: mgr.mgr_decompose_adjoint(x, g))
+
+    def fwd_bwd():
+        xr = x.detach().requires_grad_(True)
+        out = mgr.Decompose.apply(xr, None, -1)
+        (w * out * out).sum().backward()
+
+    t_fb = event_ms(torch, fwd_bwd)
+    nbytes = x.numel() * 4
+    return {"shape": list(shape), "dtype": "f32", "decompose_ms": round(t_dec, 4), "adjoint_ms": round(t_adj, 4),
+            "fwd_bwd_ms": round(t_fb, 4), "adjoint_GBps": round(nbytes / t_adj / 1e6, 2),
+            "fwd_bwd_over_decompose": round(t_fb / t_dec, 3)}
+
+
 def cpu_baseline(u_sin):
     """The CPU oracle (plain C, FP64, one thread) on one step of the headline
     workload: the 513^3 sinusoid-plus-noise field (rounded to float32, as the
@@ -205,6 +283,12 @@ def main():
 
     head = results[("f32", "sinusoid")]
     copy_gbps = copy_bandwidth(mgr, torch)
+    extra = {}
+    if not args.quick:
+        print("[bench] batched 96 fields vs serial", file=sys.stderr, flush=True)
+        extra["batched"] = batched_vs_serial(mgr, torch, synth)
+        print("[bench] adjoint / autograd at 257^3", file=sys.stderr, flush=True)
+        extra["adjoint"] = adjoint_timing(mgr, torch, synth)
     out = {
         "metric": "decompose+recompose GB/s at 513^3 fp32/fp64; % HBM peak; batched vs serial",
         "value": head["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -219,6 +303,7 @@ def main():
         "copy_kernel_GBps": round(copy_gbps, 1),
         "variants": {f"{k[0]}_{k[1]}": v for k, v in results.items()},
     }
+    out.update(extra)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(u_sin)

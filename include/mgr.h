@@ -115,6 +115,53 @@ void mgr_finalize(void);
  * previous value.  Process-wide; affects calls enqueued afterwards. */
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes);
 
+/* ---- batched decomposition ----------------------------------------------
+ * Many independent fields (any mix of shapes, dimensionalities, coordinates
+ * and level counts, one dtype) decomposed together: every workgroup-sized
+ * piece of work (field, level step, stage, block) is a work item; the items
+ * of one stage of one level step of all fields form a wave, run by one
+ * launch with a workgroup per item, and a final launch runs every field's
+ * small coarse levels.  A batch of any size is a few dozen launches, which
+ * a HIP graph captures.  Results are bit-identical to mgr_decompose on each
+ * field.  Batching is not in the paper (its large runs refactor independent
+ * partitions side by side, Sec. IV-C); the autotuner follows its
+ * model-then-measure tuning of launch shapes (Sec. III-C).
+ *
+ * Ownership: the plan owns its tables, per-field workspaces and a pinned
+ * staging buffer for the data pointers; all are allocated by
+ * mgr_batch_plan_create (synchronously), so mgr_batch_decompose allocates
+ * nothing and may be captured into a HIP graph.  A captured graph replays
+ * with the pointers of the call that was captured. */
+typedef struct mgr_batch_plan mgr_batch_plan;
+
+/* Plans a batch of nfields fields: field f has ndim[f] dimensions, sizes
+ * shapes[f][0..ndim[f]-1] (2^k+1), coordinates coords ? coords[f] : NULL (as
+ * for mgr_decompose; host memory, read during the call) and level count
+ * nlevels ? nlevels[f] : -1 (>= 1).  Writes the plan to *plan. */
+int mgr_batch_plan_create(int nfields, const int* ndim, const int64_t* const* shapes,
+                          const double* const* const* coords, const int* nlevels, int dtype,
+                          mgr_batch_plan** plan);
+
+/* dst[f] <- decomposition of src[f] for every field.  src and dst are HOST
+ * arrays of nfields device pointers (read during the call); src[f] != dst[f]
+ * (out of place).  Calls on one plan must be ordered on one stream. */
+int mgr_batch_decompose(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream);
+
+/* Autotuner: ranks the candidate chunk lengths (coarse planes per streaming
+ * item, 2..128) by a transaction model, times the best top_k on these fields
+ * (4 runs each, synchronously) and keeps the fastest.  Overwrites dst. */
+int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream,
+                       int top_k);
+
+/* Current configuration: chunk length, launches per call, work items. */
+int mgr_batch_config(const mgr_batch_plan* plan, int* chunk, int* launches, int64_t* items);
+
+/* Sets the chunk length (1..128) and rebuilds the work items. */
+int mgr_batch_set_config(mgr_batch_plan* plan, int chunk);
+
+/* Frees the plan (after synchronising with its last upload). */
+void mgr_batch_plan_destroy(mgr_batch_plan* plan);
+
 /* ---- measurement support ------------------------------------------------
  * The single-pass copy kernel the paper uses to define achievable
  * bandwidth (Sec. IV-C): dst[i] = src[i] for nbytes (a multiple of 16,

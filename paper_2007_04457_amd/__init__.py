@@ -9,7 +9,8 @@ and the current stream, the library does all the arithmetic.
 
 The C entry points are exposed under their own names (``mgr_decompose`` ...,
 taking ``src`` and ``dst`` tensors), with out-of-place conveniences
-(``decompose`` ...) and an autograd function (``Decompose``).
+(``decompose`` ...), an autograd function (``Decompose``) and the batched
+work-queue decomposition (``BatchPlan``, over ``mgr_batch_*``).
 """
 from . import _lib
 from ._lib import MgrError, MGR_F32, MGR_F64
@@ -19,7 +20,7 @@ __all__ = [
     "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_prepare",
     "mgr_class_map", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
-    "decompose", "recompose", "decompose_adjoint", "Decompose", "kernel_classes",
+    "decompose", "recompose", "decompose_adjoint", "Decompose", "kernel_classes", "BatchPlan",
 ]
 
 
@@ -211,3 +212,87 @@ class _LazyDecompose:
 
 
 Decompose = _LazyDecompose()
+
+
+class BatchPlan:
+    """Plan for decomposing many independent fields together: one launch per
+    wave of work items (``mgr_batch_plan_create`` / ``mgr_batch_decompose``).
+
+    shapes: list of shapes; coords: None or a list (per field) of per-dim
+    coordinate arrays or None; nlevels: None or a list of level counts.
+    """
+
+    def __init__(self, shapes, dtype=None, coords=None, nlevels=None):
+        import ctypes
+        torch = _torch()
+        dtype = torch.float32 if dtype is None else dtype
+        self.dtype = dtype
+        self.shapes = [tuple(int(n) for n in s) for s in shapes]
+        nf = len(self.shapes)
+        lib = _lib.load()
+        nd = (ctypes.c_int * nf)(*[len(s) for s in self.shapes])
+        shp = [_lib.shape_arg(s) for s in self.shapes]
+        shp_p = (ctypes.POINTER(ctypes.c_int64) * nf)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_int64)) for a in shp])
+        keep = []
+        cp = None
+        if coords is not None:
+            arr = (ctypes.POINTER(ctypes.POINTER(ctypes.c_double)) * nf)()
+            for f, c in enumerate(coords):
+                ptr, k = _lib.coords_arg(self.shapes[f], c)
+                keep.append(k)
+                arr[f] = ptr if ptr is not None else ctypes.POINTER(ctypes.POINTER(ctypes.c_double))()
+            cp = arr
+        nl = None if nlevels is None else (ctypes.c_int * nf)(*[int(x) for x in nlevels])
+        h = ctypes.c_void_p()
+        code = _dtype_code(torch.empty(0, dtype=dtype))
+        st = lib.mgr_batch_plan_create(nf, nd, shp_p, cp, nl, code, ctypes.byref(h))
+        del keep
+        _lib.check(st)
+        self._h = h
+
+    def _ptrs(self, ts):
+        import ctypes
+        for t, s in zip(ts, self.shapes):
+            _check(t, "field")
+            if tuple(t.shape) != s or t.dtype != self.dtype:
+                raise ValueError(f"field of shape {tuple(t.shape)} / {t.dtype}, plan has {s} / {self.dtype}")
+        if len(ts) != len(self.shapes):
+            raise ValueError("one tensor per field")
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def decompose(self, srcs, dsts=None):
+        """dsts[f] <- decomposition of srcs[f] (new tensors unless given)."""
+        torch = _torch()
+        if dsts is None:
+            dsts = [torch.empty_like(x) for x in srcs]
+        stream = torch.cuda.current_stream(srcs[0].device).cuda_stream
+        with torch.cuda.device(srcs[0].device):
+            _lib.check(_lib.load().mgr_batch_decompose(self._h, self._ptrs(srcs), self._ptrs(dsts), stream))
+        return dsts
+
+    def autotune(self, srcs, dsts, top_k=3):
+        torch = _torch()
+        stream = torch.cuda.current_stream(srcs[0].device).cuda_stream
+        _lib.check(_lib.load().mgr_batch_autotune(self._h, self._ptrs(srcs), self._ptrs(dsts), stream, int(top_k)))
+        return self.config()
+
+    def config(self):
+        """(chunk, launches per call, work items)."""
+        import ctypes
+        c, w, n = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int64(0)
+        _lib.check(_lib.load().mgr_batch_config(self._h, ctypes.byref(c), ctypes.byref(w), ctypes.byref(n)))
+        return c.value, w.value, n.value
+
+    def set_config(self, chunk):
+        _lib.check(_lib.load().mgr_batch_set_config(self._h, int(chunk)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().mgr_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -64,6 +64,22 @@ def load():
     lib.mgr_timing_read.restype = ctypes.c_int
     lib.mgr_kernel_name.argtypes = [ctypes.c_int]
     lib.mgr_kernel_name.restype = ctypes.c_char_p
+    i32p = ctypes.POINTER(ctypes.c_int)
+    lib.mgr_batch_plan_create.argtypes = [ctypes.c_int, i32p, ctypes.POINTER(i64p),
+                                          ctypes.POINTER(dpp), i32p, ctypes.c_int,
+                                          ctypes.POINTER(vp)]
+    lib.mgr_batch_plan_create.restype = ctypes.c_int
+    vpp = ctypes.POINTER(vp)
+    lib.mgr_batch_decompose.argtypes = [vp, vpp, vpp, vp]
+    lib.mgr_batch_decompose.restype = ctypes.c_int
+    lib.mgr_batch_autotune.argtypes = [vp, vpp, vpp, vp, ctypes.c_int]
+    lib.mgr_batch_autotune.restype = ctypes.c_int
+    lib.mgr_batch_config.argtypes = [vp, i32p, i32p, ctypes.POINTER(ctypes.c_int64)]
+    lib.mgr_batch_config.restype = ctypes.c_int
+    lib.mgr_batch_set_config.argtypes = [vp, ctypes.c_int]
+    lib.mgr_batch_set_config.restype = ctypes.c_int
+    lib.mgr_batch_plan_destroy.argtypes = [vp]
+    lib.mgr_batch_plan_destroy.restype = None
     _lib = lib
     return lib
 

@@ -8,6 +8,7 @@
 // (m_d + 1) / 2, which the driver keeps packed in workspace buffers W_{k+1}.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -575,9 +576,9 @@ SolveTables<T> solve_tables_of(const Plan& p, int k, int d)
 // Correction buffer of level step k (even and odd steps alternate so that a
 // step can read the previous step's correction while writing its own).
 template <typename T>
-T* corr(const Plan& p, int k)
+T* corr(const Plan& p, int k, void* ws = nullptr)
 {
-    return (T*)p.ws + ((k & 1) ? p.F2 : p.F);
+    return (T*)(ws ? ws : p.ws) + ((k & 1) ? p.F2 : p.F);
 }
 
 // Streaming level kernel of level step k: coefficients + load vector (dec,
@@ -681,11 +682,11 @@ int tail_start(const Plan& p)
 }
 
 template <typename T>
-TailArgs<T> tail_args(const Plan& p, int k0, const T* src, T* dst)
+TailArgs<T> tail_args(const Plan& p, int k0, const T* src, T* dst, void* wsp = nullptr)
 {
     TailArgs<T> a;
     std::memset(&a, 0, sizeof(a));
-    T* ws = (T*)p.ws;
+    T* ws = (T*)(wsp ? wsp : p.ws);
     const T* base = (const T*)p.tables;
     a.k0 = k0;
     a.nlev = p.nlevels - k0;
@@ -879,7 +880,377 @@ int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const in
 
 const char* const kKernelNames[KC_COUNT] = {
     "coef_decompose", "solve", "interp_recompose",
-    "masstrans_t", "adj_combine", "copy_view", "bench_copy", "stream_dec", "stream_load", "tail"};
+    "masstrans_t", "adj_combine", "copy_view", "bench_copy", "stream_dec", "stream_load", "tail", "batch"};
+
+// ---- batched decomposition (waves of work items, mgr_batch.hip) --------------
+constexpr int kStagesPerLevel = 10;  // stream + up to three solves of up to three phases
+constexpr int kMaxBatchChunk = 128;  // coarse planes per streaming item (the kernel's LDS tables)
+
+struct BatchPlan {
+    int dtype = 0, nfields = 0, device = 0;
+    std::vector<Plan*> plans;
+    std::vector<int> kt;           // first tail level step per field
+    std::vector<size_t> wsoff;     // byte offset of each field's workspace
+    void* ws = nullptr;            // the fields' workspaces (same layout as their plans')
+    void* dev = nullptr;           // device tables (one allocation)
+    void* host_ptrs = nullptr;     // pinned staging of the per-call pointers
+    size_t off_items = 0, off_sargs = 0, off_solves = 0, off_scat = 0, off_tail = 0, off_tailf = 0, off_ptrs = 0,
+           off_args = 0, dev_bytes = 0;
+    std::vector<std::pair<int, int>> waves;  // (first item, items) per launch
+    int n_items = 0, n_tail = 0;
+    int chunk = 8, tuned = 0;
+    int64_t bytes = 0;             // input bytes of the batch
+    hipEvent_t staged = nullptr;   // the pointer upload of the last call
+    bool staged_pending = false;
+};
+
+template <typename T>
+struct BatchTables {
+    std::vector<BatchItem> items;
+    std::vector<std::pair<int, int>> waves;
+    std::vector<StreamArgs<T>> sargs;
+    std::vector<BatchSolve<T>> solves;
+    std::vector<BatchScatter<T>> scatters;
+    std::vector<TailArgs<T>> tail;
+    std::vector<int> tailf;
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Work items of every field, grouped into waves (level step k, stage s) in
+// that order; within a wave, field by field.
+template <typename T>
+int batch_tables(BatchPlan& b, int chunk, BatchTables<T>& out)
+{
+    const int nf = b.nfields;
+    int maxL = 1;
+    for (int f = 0; f < nf; f++) maxL = std::max(maxL, b.plans[(size_t)f]->nlevels);
+    std::vector<std::vector<std::vector<std::vector<BatchItem>>>> st((size_t)nf);
+    for (int f = 0; f < nf; f++) {
+        const Plan& p = *b.plans[(size_t)f];
+        void* wsf = (char*)b.ws + b.wsoff[(size_t)f];
+        T* ws = (T*)wsf;
+        st[(size_t)f].resize((size_t)b.kt[(size_t)f]);
+        for (int k = 0; k < b.kt[(size_t)f]; k++) {
+            const LevelLayout& ly = p.lv[(size_t)k];
+            auto& stages = st[(size_t)f][(size_t)k];
+            // streaming stage
+            StreamArgs<T> a;
+            std::memset(&a, 0, sizeof(a));
+            a.A = (k == 0) ? nullptr : ws + p.Woff[(size_t)k];
+            a.Z = (k == 0) ? nullptr : corr<T>(p, k - 1, wsf);
+            a.av = (k == 0) ? full_view(p) : packed(ly.m);
+            a.C = nullptr;
+            a.cv = level_view(p, k);
+            a.W = ws + p.Woff[(size_t)k + 1];
+            a.wv = packed(ly.mc);
+            a.F = corr<T>(p, k, wsf);
+            a.fv = packed(ly.mc);
+            a.tb = tables_of<T>(p, k);
+            a.write_coarse = (k == 0) ? 1 : 0;
+            const bool act0 = a.av.n[0] > 1, act1 = a.av.n[1] > 1;
+            int kT1, kT2;
+            level_tiling(act1, &kT1, &kT2);
+            a.nt1 = act1 ? (int)cdiv(a.fv.n[1], kT1) : 1;
+            a.nt2 = (int)cdiv(a.fv.n[2], kT2);
+            const int c0 = (int)a.fv.n[0];
+            a.chunk = act0 ? std::min(std::max(chunk, 2), c0) : c0;
+            a.nch = act0 ? (int)cdiv(c0, a.chunk) : 1;
+            const int sidx = (int)out.sargs.size();
+            out.sargs.push_back(a);
+            std::vector<BatchItem> s0;
+            const int type = (act0 && act1) ? BI_STREAM3 : act0 ? BI_STREAM2 : BI_STREAM1;
+            for (int t = 0; t < a.nt1 * a.nt2 * a.nch; t++) s0.push_back(BatchItem{type, sidx, t, 0, f});
+            stages.push_back(std::move(s0));
+            // correction solves, dimensions last to first
+            for (int d = 2; d >= 0; d--) {
+                if (!p.active[d]) continue;
+                BatchSolve<T> bs;
+                std::memset(&bs, 0, sizeof(bs));
+                bs.F = corr<T>(p, k, wsf);
+                bs.n = ly.mc[d];
+                bs.inner = 1;
+                for (int e = d + 1; e < 3; e++) bs.inner *= ly.mc[e];
+                bs.outer = 1;
+                for (int e = 0; e < d; e++) bs.outer *= ly.mc[e];
+                bs.nfib = bs.inner * bs.outer;
+                bs.tb = solve_tables_of<T>(p, k, d);
+                bs.Yb = ws + p.Yb;
+                const int S = bs.tb.S;
+                const int vidx = (int)out.solves.size();
+                if (bs.inner == 1 && S <= kThreadsBatch && bs.n <= kBatchRowSpan) {
+                    bs.rows = (int)std::max<int64_t>(1, std::min<int64_t>(kThreadsBatch / S, kBatchRowSpan / bs.n));
+                    std::vector<BatchItem> sg;
+                    for (int64_t x = 0; x < cdiv(bs.nfib, bs.rows); x++) sg.push_back(BatchItem{BI_ROWS, vidx, (int)x, 0, f});
+                    stages.push_back(std::move(sg));
+                } else if (bs.inner > 1 && S <= 16) {
+                    std::vector<BatchItem> sg;
+                    for (int64_t x = 0; x < cdiv(bs.nfib, 16); x++) sg.push_back(BatchItem{BI_STRIDED, vidx, (int)x, 0, f});
+                    stages.push_back(std::move(sg));
+                } else {
+                    std::vector<BatchItem> s1, s2, s3;
+                    if (bs.inner > 1) {
+                        for (int y = 0; y < S; y++)
+                            for (int64_t x = 0; x < cdiv(bs.nfib, kThreadsBatch); x++) {
+                                s1.push_back(BatchItem{BI_SEG_ENDS, vidx, (int)x, y, f});
+                                s3.push_back(BatchItem{BI_SEG_FINAL, vidx, (int)x, y, f});
+                            }
+                    } else {
+                        for (int64_t x = 0; x < cdiv(bs.nfib * S, kThreadsBatch); x++) {
+                            s1.push_back(BatchItem{BI_SEG_ENDS, vidx, (int)x, 0, f});
+                            s3.push_back(BatchItem{BI_SEG_FINAL, vidx, (int)x, 0, f});
+                        }
+                    }
+                    for (int64_t x = 0; x < cdiv(bs.nfib, kThreadsBatch); x++)
+                        s2.push_back(BatchItem{BI_SEPARATORS, vidx, (int)x, 0, f});
+                    stages.push_back(std::move(s1));
+                    stages.push_back(std::move(s2));
+                    stages.push_back(std::move(s3));
+                }
+                out.solves.push_back(bs);
+            }
+            if ((int)stages.size() > kStagesPerLevel) return fail(MGR_ERR_ARG, "too many stages per level step");
+        }
+    }
+    // waves: level step, stage, field
+    for (int k = 0; k < maxL; k++)
+        for (int s = 0; s < kStagesPerLevel; s++) {
+            const int first = (int)out.items.size();
+            for (int f = 0; f < nf; f++) {
+                if (k >= b.kt[(size_t)f]) continue;
+                auto& stages = st[(size_t)f][(size_t)k];
+                if (s >= (int)stages.size()) continue;
+                out.items.insert(out.items.end(), stages[(size_t)s].begin(), stages[(size_t)s].end());
+            }
+            const int n = (int)out.items.size() - first;
+            if (n > 0) out.waves.emplace_back(first, n);
+        }
+    // fields whose every level step streamed: coarsest values to their nodes
+    {
+        const int first = (int)out.items.size();
+        for (int f = 0; f < nf; f++) {
+            const Plan& p = *b.plans[(size_t)f];
+            const int L = p.nlevels;
+            if (b.kt[(size_t)f] < L) continue;
+            void* wsf = (char*)b.ws + b.wsoff[(size_t)f];
+            const View3 cl = level_view(p, L);
+            BatchScatter<T> sc;
+            sc.W = (const T*)wsf + p.Woff[(size_t)L];
+            sc.Z = corr<T>(p, L - 1, wsf);
+            for (int d = 0; d < 3; d++) {
+                sc.n[d] = cl.n[d];
+                sc.ds[d] = cl.s[d];
+            }
+            const int idx = (int)out.scatters.size();
+            out.scatters.push_back(sc);
+            for (int64_t x = 0; x < cdiv(cl.n[0] * cl.n[1] * cl.n[2], kThreadsBatch); x++)
+                out.items.push_back(BatchItem{BI_SCATTER, idx, (int)x, 0, f});
+        }
+        const int n = (int)out.items.size() - first;
+        if (n > 0) out.waves.emplace_back(first, n);
+    }
+    if (out.items.size() > (size_t)INT32_MAX) return fail(MGR_ERR_ARG, "too many work items");
+    // small level steps: one tail workgroup per field that has them
+    for (int f = 0; f < nf; f++) {
+        const Plan& p = *b.plans[(size_t)f];
+        const int kt = b.kt[(size_t)f];
+        if (kt >= p.nlevels) continue;
+        void* wsf = (char*)b.ws + b.wsoff[(size_t)f];
+        TailArgs<T> a = tail_args<T>(p, kt, nullptr, nullptr, wsf);
+        a.Z0 = (kt == 0) ? nullptr : corr<T>(p, kt - 1, wsf);
+        out.tail.push_back(a);
+        out.tailf.push_back(f);
+    }
+    return MGR_OK;
+}
+
+template <typename T>
+int batch_upload(BatchPlan& b, int chunk)
+{
+    BatchTables<T> t;
+    int rc = batch_tables<T>(b, chunk, t);
+    if (rc) return rc;
+    const size_t al = 256;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, al);
+        return o;
+    };
+    b.off_items = take(sizeof(BatchItem) * t.items.size());
+    b.off_sargs = take(sizeof(StreamArgs<T>) * t.sargs.size());
+    b.off_solves = take(sizeof(BatchSolve<T>) * t.solves.size());
+    b.off_scat = take(sizeof(BatchScatter<T>) * t.scatters.size());
+    b.off_tail = take(sizeof(TailArgs<T>) * t.tail.size());
+    b.off_tailf = take(sizeof(int) * t.tailf.size());
+    b.off_ptrs = take(2 * sizeof(void*) * (size_t)b.nfields);
+    b.off_args = take(sizeof(BatchKernelArgs<T>));
+    if (b.dev) (void)hipFree(b.dev);
+    b.dev = nullptr;
+    hipError_t e = hipMalloc(&b.dev, off);
+    if (e != hipSuccess) {
+        b.dev = nullptr;
+        return fail(MGR_ERR_ALLOC, std::string("hipMalloc batch tables: ") + hipGetErrorString(e));
+    }
+    b.dev_bytes = off;
+    char* d = (char*)b.dev;
+    BatchKernelArgs<T> ka;
+    ka.items = (const BatchItem*)(d + b.off_items);
+    ka.sargs = (const StreamArgs<T>*)(d + b.off_sargs);
+    ka.solves = (const BatchSolve<T>*)(d + b.off_solves);
+    ka.scatters = (const BatchScatter<T>*)(d + b.off_scat);
+    ka.src = (const T* const*)(d + b.off_ptrs);
+    ka.dst = (T* const*)(d + b.off_ptrs + sizeof(void*) * (size_t)b.nfields);
+    struct Part {
+        size_t off;
+        const void* src;
+        size_t bytes;
+    } parts[] = {{b.off_items, t.items.data(), sizeof(BatchItem) * t.items.size()},
+                 {b.off_sargs, t.sargs.data(), sizeof(StreamArgs<T>) * t.sargs.size()},
+                 {b.off_solves, t.solves.data(), sizeof(BatchSolve<T>) * t.solves.size()},
+                 {b.off_scat, t.scatters.data(), sizeof(BatchScatter<T>) * t.scatters.size()},
+                 {b.off_tail, t.tail.data(), sizeof(TailArgs<T>) * t.tail.size()},
+                 {b.off_tailf, t.tailf.data(), sizeof(int) * t.tailf.size()},
+                 {b.off_args, &ka, sizeof(ka)}};
+    for (const Part& pt : parts) {
+        if (!pt.bytes) continue;
+        e = hipMemcpy(d + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+    }
+    b.waves = t.waves;
+    b.n_items = (int)t.items.size();
+    b.n_tail = (int)t.tail.size();
+    b.chunk = chunk;
+    return MGR_OK;
+}
+
+void free_batch(BatchPlan* b)
+{
+    if (!b) return;
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->ws) (void)hipFree(b->ws);
+    if (b->host_ptrs) (void)hipHostFree(b->host_ptrs);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+}
+
+template <typename T>
+int batch_run(BatchPlan& b, const void* const* src, void* const* dst, hipStream_t st)
+{
+    const int nf = b.nfields;
+    const bool cap = capturing(st);
+    if (b.staged_pending && !cap) {
+        // the previous call's upload must have read the staging buffer
+        hipError_t e = hipEventSynchronize(b.staged);
+        if (e != hipSuccess) return hip_fail(e, "batch staging");
+    }
+    void** hp = (void**)b.host_ptrs;
+    for (int f = 0; f < nf; f++) {
+        hp[f] = const_cast<void*>(src[f]);
+        hp[nf + f] = dst[f];
+    }
+    char* d = (char*)b.dev;
+    MGR_TRY(hipMemcpyAsync(d + b.off_ptrs, hp, 2 * sizeof(void*) * (size_t)nf, hipMemcpyHostToDevice, st),
+            "batch pointer upload");
+    if (!cap) {
+        MGR_TRY(hipEventRecord(b.staged, st), "batch staging event");
+        b.staged_pending = true;
+    }
+    const BatchKernelArgs<T>* dev_args = (const BatchKernelArgs<T>*)(d + b.off_args);
+    for (size_t w = 0; w < b.waves.size(); w++) {
+        const int first = b.waves[w].first, n = b.waves[w].second;
+        MGR_TRY(timed(KC_BATCH, (int)w, st, [&] { return launch_batch_wave<T>(dev_args, first, n, st); }),
+                "batch wave launch");
+    }
+    MGR_TRY(timed(KC_TAIL, -1, st,
+                  [&] {
+                      return launch_tail_batch<T>((const TailArgs<T>*)(d + b.off_tail), (const int*)(d + b.off_tailf),
+                                                  (const T* const*)(d + b.off_ptrs),
+                                                  (T* const*)(d + b.off_ptrs + sizeof(void*) * (size_t)nf), b.n_tail,
+                                                  true, st);
+                  }),
+            "batch tail launch");
+    return MGR_OK;
+}
+
+int batch_create(int nfields, const int* ndim, const int64_t* const* shapes, const double* const* const* coords,
+                 const int* nlevels, int dtype, BatchPlan** out)
+{
+    if (!out) return fail(MGR_ERR_ARG, "plan is NULL");
+    *out = nullptr;
+    if (nfields <= 0 || !ndim || !shapes) return fail(MGR_ERR_ARG, "nfields, ndim or shapes invalid");
+    auto b = std::unique_ptr<BatchPlan, void (*)(BatchPlan*)>(new BatchPlan, free_batch);
+    b->dtype = dtype;
+    b->nfields = nfields;
+    size_t ws_total = 0;
+    const size_t esz = (dtype == MGR_F64) ? 8 : 4;
+    for (int f = 0; f < nfields; f++) {
+        Plan* p = nullptr;
+        int rc = get_plan(dtype, ndim[f], shapes[f], coords ? coords[f] : nullptr, nlevels ? nlevels[f] : -1, nullptr,
+                          false, &p);
+        if (rc) return fail(rc, "field " + std::to_string(f) + ": " + g_err);
+        if (p->nlevels == 0) return fail(MGR_ERR_LEVELS, "field " + std::to_string(f) + ": batches need nlevels >= 1");
+        const int kt = tail_start(*p);  // as the per-field path, so results agree bit for bit
+        b->plans.push_back(p);
+        b->kt.push_back(kt);
+        b->wsoff.push_back(ws_total);
+        ws_total = align_up(ws_total + p->ws_bytes, 256);
+        b->bytes += (int64_t)(p->n[0] * p->n[1] * p->n[2]) * (int64_t)esz;
+    }
+    if (ws_total > workspace_cap()) return fail(MGR_ERR_ALLOC, "batch workspace exceeds MGR_WORKSPACE_MAX");
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipMalloc(&b->ws, std::max<size_t>(ws_total, 256));
+    if (e != hipSuccess) {
+        b->ws = nullptr;
+        return fail(MGR_ERR_ALLOC, std::string("hipMalloc batch workspace: ") + hipGetErrorString(e));
+    }
+    e = hipHostMalloc(&b->host_ptrs, 2 * sizeof(void*) * (size_t)nfields, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        b->host_ptrs = nullptr;
+        return fail(MGR_ERR_ALLOC, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        b->staged = nullptr;
+        return hip_fail(e, "hipEventCreate");
+    }
+    int rc = (dtype == MGR_F64) ? batch_upload<double>(*b, 8) : batch_upload<float>(*b, 8);
+    if (rc) return rc;
+    *out = b.release();
+    return MGR_OK;
+}
+
+// The transaction model of the batch's streaming items (the paper's
+// performance-model pruning of thread-block shapes, Sec. III-C, applied to
+// the chunk of coarse planes per item): bytes moved, with the 3-plane halo of
+// every item, at the streaming kernel's bandwidth, plus a fixed cost per
+// item spread over the device's workgroup slots.
+double batch_model_us(const BatchPlan& b, int chunk)
+{
+    const double bw = 5.0e3;    // bytes per microsecond moved by the streaming kernel
+    const double t_item = 2.0;  // microseconds of start-up and drain per item
+    double bytes = 0.0, items = 0.0;
+    const double esz = (b.dtype == MGR_F64) ? 8.0 : 4.0;
+    for (int f = 0; f < b.nfields; f++) {
+        const Plan& p = *b.plans[(size_t)f];
+        for (int k = 0; k < b.kt[(size_t)f]; k++) {
+            const LevelLayout& ly = p.lv[(size_t)k];
+            const double V = (double)(ly.m[0] * ly.m[1] * ly.m[2]);
+            const double c0 = (double)ly.mc[0];
+            const bool act0 = ly.m[0] > 1, act1 = ly.m[1] > 1;
+            int kT1, kT2;
+            level_tiling(act1, &kT1, &kT2);
+            const double tiles = (act1 ? std::ceil((double)ly.mc[1] / kT1) : 1.0) * std::ceil((double)ly.mc[2] / kT2);
+            const double ch = act0 ? std::min<double>(std::max(chunk, 2), c0) : c0;
+            const double nch = act0 ? std::ceil(c0 / ch) : 1.0;
+            const double halo = act0 ? (2.0 * ch + 3.0) / (2.0 * ch) : 1.0;
+            bytes += 2.0 * V * esz * halo;
+            items += tiles * nch;
+        }
+    }
+    return bytes / bw + t_item * items / (4.0 * device_cu_count());
+}
 
 }  // namespace
 }  // namespace mgr
@@ -1065,6 +1436,124 @@ const char* mgr_kernel_name(int kernel)
 {
     if (kernel < 0 || kernel >= KC_COUNT) return nullptr;
     return kKernelNames[kernel];
+}
+
+int mgr_batch_plan_create(int nfields, const int* ndim, const int64_t* const* shapes,
+                          const double* const* const* coords, const int* nlevels, int dtype, mgr_batch_plan** plan)
+{
+    try {
+        g_err.clear();
+        if (dtype != MGR_F32 && dtype != MGR_F64) return fail(MGR_ERR_ARG, "dtype must be MGR_F32 or MGR_F64");
+        BatchPlan* b = nullptr;
+        int rc = batch_create(nfields, ndim, shapes, coords, nlevels, dtype, &b);
+        if (plan) *plan = reinterpret_cast<mgr_batch_plan*>(b);
+        return rc;
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_batch_decompose(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream)
+{
+    try {
+        g_err.clear();
+        BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+        if (!b || !src || !dst) return fail(MGR_ERR_ARG, "plan, src or dst is NULL");
+        for (int f = 0; f < b->nfields; f++) {
+            if (!src[f] || !dst[f]) return fail(MGR_ERR_ARG, "NULL data pointer for field " + std::to_string(f));
+            if (src[f] == dst[f]) return fail(MGR_ERR_ARG, "batched decomposition is out of place (field " +
+                                                               std::to_string(f) + ")");
+        }
+        hipStream_t st = (hipStream_t)stream;
+        return b->dtype == MGR_F64 ? batch_run<double>(*b, src, dst, st) : batch_run<float>(*b, src, dst, st);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream, int top_k)
+{
+    try {
+        g_err.clear();
+        BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+        if (!b || !src || !dst) return fail(MGR_ERR_ARG, "plan, src or dst is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        if (capturing(st)) return fail(MGR_ERR_CAPTURE, "autotuning times launches; not during capture");
+        const int cand[] = {2, 4, 8, 16, 32, 64, 128};
+        std::vector<std::pair<double, int>> ranked;
+        for (int c : cand) ranked.emplace_back(batch_model_us(*b, c), c);
+        std::sort(ranked.begin(), ranked.end());
+        if (top_k < 1) top_k = 3;
+        top_k = std::min<int>(top_k, (int)ranked.size());
+        hipEvent_t e0, e1;
+        MGR_TRY(hipEventCreate(&e0), "event");
+        MGR_TRY(hipEventCreate(&e1), "event");
+        double best = 1e300;
+        int best_chunk = b->chunk, rc = MGR_OK;
+        for (int i = 0; i < top_k && rc == MGR_OK; i++) {
+            const int c = ranked[(size_t)i].second;
+            rc = b->dtype == MGR_F64 ? batch_upload<double>(*b, c) : batch_upload<float>(*b, c);
+            if (rc) break;
+            std::vector<float> ms;
+            for (int r = 0; r < 4 && rc == MGR_OK; r++) {
+                (void)hipEventRecord(e0, st);
+                rc = mgr_batch_decompose(plan, src, dst, stream);
+                (void)hipEventRecord(e1, st);
+                float t = 0.f;
+                if (rc == MGR_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                    ms.push_back(t);
+            }
+            if (ms.size() > 1) {
+                std::sort(ms.begin() + 1, ms.end());  // the first run is a warm-up
+                const double med = ms[1 + (ms.size() - 1) / 2];
+                if (med < best) {
+                    best = med;
+                    best_chunk = c;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        rc = b->dtype == MGR_F64 ? batch_upload<double>(*b, best_chunk) : batch_upload<float>(*b, best_chunk);
+        if (rc == MGR_OK) b->tuned = 1;
+        return rc;
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_batch_config(const mgr_batch_plan* plan, int* chunk, int* launches, int64_t* items)
+{
+    const BatchPlan* b = reinterpret_cast<const BatchPlan*>(plan);
+    if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
+    if (chunk) *chunk = b->chunk;
+    if (launches) *launches = (int)b->waves.size() + 1;
+    if (items) *items = b->n_items;
+    return MGR_OK;
+}
+
+int mgr_batch_set_config(mgr_batch_plan* plan, int chunk)
+{
+    try {
+        g_err.clear();
+        BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+        if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
+        if (chunk < 1 || chunk > kMaxBatchChunk) return fail(MGR_ERR_ARG, "chunk must be 1.." + std::to_string(kMaxBatchChunk));
+        return b->dtype == MGR_F64 ? batch_upload<double>(*b, chunk) : batch_upload<float>(*b, chunk);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+void mgr_batch_plan_destroy(mgr_batch_plan* plan)
+{
+    BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+    if (!b) return;
+    if (b->staged_pending) (void)hipEventSynchronize(b->staged);
+    free_batch(b);
 }
 
 }  // extern "C"

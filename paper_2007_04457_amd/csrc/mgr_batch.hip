@@ -1,0 +1,172 @@
+// Batched decomposition of many independent fields.
+//
+// The host lists every workgroup-sized piece of work of every field (the
+// streaming level tiles and the correction-solve blocks of each level step)
+// as an item, grouped into waves: wave (k, s) holds stage s of level step k
+// of every field that has it (stage 0 the streaming pass, then the solves).
+// One launch runs a wave, one workgroup per item, whatever its field, shape
+// or dimensionality; stream order between the waves carries every
+// dependency (stage s of a field needs its stage s - 1, level step k + 1
+// needs the last solve of step k), so no workgroup ever waits for another.
+// The whole sequence (a few dozen launches for any number of fields) is
+// what a HIP graph captures.
+#include "mgr_solve_dev.h"
+#include "mgr_stream_dev.h"
+
+namespace mgr {
+namespace {
+
+template <typename T>
+union BatchSmem {
+    LevelSmem<T, true, true, true> lv3;
+    LevelSmem<T, true, false, true> lv2;
+    LevelSmem<T, false, false, true> lv1;
+    StridedSmem<T> str;
+    RowsSmem<T, kBatchRowSpan, true> rows_t;
+    RowsSmem<T, kBatchRowSpan, false> rows_g;
+};
+
+// The kernel's LDS (dynamic, sized to BatchSmem<T> at launch).  Each item
+// type runs in a function of its own (not inlined), so that its registers
+// are allocated on its own: the kernel's register budget is then set by the
+// largest item, and items above it spill inside themselves only.
+extern __shared__ __align__(16) unsigned char batch_lds[];
+
+// Copy of a wave-uniform struct in scalar registers (the item functions
+// reach their arguments through generic pointers, whose loads land in vector
+// registers).
+template <class S>
+__device__ __forceinline__ S load_uniform(const S* p)
+{
+    static_assert(sizeof(S) % 4 == 0, "whole dwords");
+    S out;
+    int* o = reinterpret_cast<int*>(&out);
+    const int* q = reinterpret_cast<const int*>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(S) / 4); i++) o[i] = __builtin_amdgcn_readfirstlane(q[i]);
+    return out;
+}
+
+template <typename T, bool kAct0, bool kAct1>
+__device__ __attribute__((noinline)) void exec_stream(const BatchKernelArgs<T>* A, const BatchItem* itp)
+{
+    auto& sm = *reinterpret_cast<LevelSmem<T, kAct0, kAct1, true>*>(batch_lds);
+    const BatchItem it = load_uniform(itp);
+    StreamArgs<T> a = load_uniform(A->sargs + it.args);
+    if (!a.A) a.A = load_uniform(A->src + it.field);
+    a.C = load_uniform(A->dst + it.field);
+    if (a.Z)
+        stream_level_tile<T, kAct0, kAct1, true, true>(a, it.bx, sm);
+    else
+        stream_level_tile<T, kAct0, kAct1, true, false>(a, it.bx, sm);
+}
+
+template <typename T>
+__device__ __forceinline__ FibreMap fibre_map(const BatchSolve<T>& b)
+{
+    FibreMap m;
+    m.n = b.n;
+    m.inner = b.inner;
+    m.outer = b.outer;
+    m.nfib = b.nfib;
+    m.S = b.tb.S;
+    return m;
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) void exec_rows(const BatchKernelArgs<T>* A, const BatchItem* itp)
+{
+    const BatchItem it = load_uniform(itp);
+    const BatchSolve<T> b = load_uniform(A->solves + it.args);
+    const FibreMap m = fibre_map(b);
+    const int64_t row0 = (int64_t)it.bx * b.rows;
+    const int nrows = (int)min((int64_t)b.rows, m.nfib - row0);
+    if (m.S <= kMaxSegWG)
+        solve_rows_tile<T, kBatchRowSpan, true>(
+            b.F, m, b.tb, row0, nrows, *reinterpret_cast<RowsSmem<T, kBatchRowSpan, true>*>(batch_lds));
+    else
+        solve_rows_tile<T, kBatchRowSpan, false>(
+            b.F, m, b.tb, row0, nrows, *reinterpret_cast<RowsSmem<T, kBatchRowSpan, false>*>(batch_lds));
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) void exec_strided(const BatchKernelArgs<T>* A, const BatchItem* itp)
+{
+    const BatchItem it = load_uniform(itp);
+    const BatchSolve<T> b = load_uniform(A->solves + it.args);
+    const int tid = threadIdx.x;
+    solve_strided_tile<T, 16, false>(b.F, fibre_map(b), b.tb, (int64_t)it.bx * 16, tid / 16, tid % 16, kThreads,
+                                     tid, *reinterpret_cast<StridedSmem<T>*>(batch_lds));
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) void exec_phase(const BatchKernelArgs<T>* A, const BatchItem* itp)
+{
+    const BatchItem it = load_uniform(itp);
+    const BatchSolve<T> b = load_uniform(A->solves + it.args);
+    const FibreMap m = fibre_map(b);
+    if (it.type == BI_SEG_ENDS)
+        seg_ends_tile(b.F, b.Yb, m, b.tb, it.bx, it.by);
+    else if (it.type == BI_SEPARATORS)
+        separators_tile(b.F, b.Yb, m, b.tb, it.bx);
+    else
+        seg_final_tile(b.F, m, b.tb, it.bx, it.by);
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) void exec_scatter(const BatchKernelArgs<T>* A, const BatchItem* itp)
+{
+    const BatchItem it = load_uniform(itp);
+    const BatchScatter<T> sc = load_uniform(A->scatters + it.args);
+    T* dst = load_uniform(A->dst + it.field);
+    const int64_t idx = (int64_t)it.bx * kThreads + threadIdx.x;
+    if (idx >= sc.n[0] * sc.n[1] * sc.n[2]) return;
+    const int64_t j2 = idx % sc.n[2], j1 = (idx / sc.n[2]) % sc.n[1], j0 = idx / (sc.n[1] * sc.n[2]);
+    dst[j0 * sc.ds[0] + j1 * sc.ds[1] + j2 * sc.ds[2]] = sc.W[idx] + sc.Z[idx];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_batch(const BatchKernelArgs<T>* __restrict__ A, int first)
+{
+    const BatchItem* itp = A->items + first + blockIdx.x;
+    switch (itp->type) {
+        case BI_STREAM3: exec_stream<T, true, true>(A, itp); break;
+        case BI_STREAM2: exec_stream<T, true, false>(A, itp); break;
+        case BI_STREAM1: exec_stream<T, false, false>(A, itp); break;
+        case BI_ROWS: exec_rows<T>(A, itp); break;
+        case BI_STRIDED: exec_strided<T>(A, itp); break;
+        case BI_SCATTER: exec_scatter<T>(A, itp); break;
+        default: exec_phase<T>(A, itp); break;
+    }
+}
+
+}  // namespace
+
+int device_cu_count()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+// One wave of items: dev_a (device memory) lists them; this launch runs
+// items [first, first + n).
+template <typename T>
+hipError_t launch_batch_wave(const BatchKernelArgs<T>* dev_a, int first, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)n), dim3(kThreads), sizeof(BatchSmem<T>), st, dev_a, first);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_wave<float>(const BatchKernelArgs<float>*, int, int, hipStream_t);
+template hipError_t launch_batch_wave<double>(const BatchKernelArgs<double>*, int, int, hipStream_t);
+
+}  // namespace mgr

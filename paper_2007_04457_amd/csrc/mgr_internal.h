@@ -117,11 +117,80 @@ struct TailArgs {
 
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& a, bool decompose, hipStream_t st);
+// One workgroup per entry: dev_args[i] in device memory, applied to field
+// field[i] of the per-field pointer tables src / dst (device memory).
+template <typename T>
+hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, const T* const* src, T* const* dst,
+                             int n, bool decompose, hipStream_t st);
 
 template <typename T>
 hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
+// Coarse rows and columns per streaming tile (act1: the problem has a
+// second active dimension); workgroup id = (chunk * nt1 + t1) * nt2 + t2.
+void level_tiling(bool act1, int* kT1, int* kT2);
 template <typename T>
 hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st);
+
+// ---- batched decomposition (mgr_batch.hip) ----------------------------------
+// Work items: one workgroup's share of one stage of one level step of one
+// field.  Items are grouped into waves (level step k, stage s) over all
+// fields; one launch per wave, stream order between waves.
+enum BatchItemType {
+    BI_STREAM3 = 0,  // streaming level tile, 3-D problem
+    BI_STREAM2,      // 2-D problem (m0, 1, m2)
+    BI_STREAM1,      // 1-D problem
+    BI_ROWS,         // solve along the contiguous dimension, a block of rows
+    BI_STRIDED,      // solve along a strided dimension, 16 fibres (S <= 16)
+    BI_SEG_ENDS,     // long fibres, three phases (three waves)
+    BI_SEPARATORS,
+    BI_SEG_FINAL,
+    BI_SCATTER,      // coarsest values W_L + z_{L-1} to their nodes (fields without a tail)
+    BI_COUNT
+};
+
+struct BatchItem {
+    int type;
+    int args;    // index into the stream or solve argument table
+    int bx, by;  // the workgroup's share: stream tile id; solve block (x, y)
+    int field;   // field index (for the caller's data pointers)
+};
+
+template <typename T>
+struct BatchSolve {
+    T* F;  // packed correction array of the level step
+    int64_t n, inner, outer, nfib;
+    SolveTables<T> tb;
+    T* Yb;     // segment-end buffer of the three-phase form
+    int rows;  // rows per item (contiguous dimension)
+};
+
+template <typename T>
+struct BatchScatter {
+    const T* W;  // packed coarsest grid
+    const T* Z;  // correction of the last level step, same layout
+    int64_t n[3];
+    int64_t ds[3];  // strides of the coarsest nodes in the field's dst
+};
+
+template <typename T>
+struct BatchKernelArgs {
+    const BatchItem* items;
+    const StreamArgs<T>* sargs;  // A == nullptr: read the field's src; C is the field's dst
+    const BatchSolve<T>* solves;
+    const BatchScatter<T>* scatters;
+    const T* const* src;  // per field
+    T* const* dst;
+};
+
+// Threads of a batch workgroup, and elements of a row block staged by a
+// batched contiguous-dimension solve item.
+constexpr int kThreadsBatch = 256;
+constexpr int kBatchRowSpan = 4096;
+
+// Runs items [first, first + n) of the table dev_a->items, one workgroup each.
+template <typename T>
+hipError_t launch_batch_wave(const BatchKernelArgs<T>* dev_a, int first, int n, hipStream_t st);
+int device_cu_count();
 
 // Kernel classes (for timing and profiling names).
 enum KernelClass {
@@ -135,6 +204,7 @@ enum KernelClass {
     KC_STREAM_DEC,
     KC_STREAM_LOAD,
     KC_TAIL,
+    KC_BATCH,
     KC_COUNT
 };
 

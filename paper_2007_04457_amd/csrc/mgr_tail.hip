@@ -220,10 +220,8 @@ __device__ Regions<T> carve(T* sbuf, const TailLevel<T>& L0)
 }
 
 template <typename T, bool kDec>
-__global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
+__device__ __forceinline__ void tail_body(const TailArgs<T>& a, const T* src, T* dst, T* sbuf, T* stab)
 {
-    __shared__ T sbuf[kTailDataElems];
-    __shared__ T stab[kTailTabElems];
     const Regions<T> R = carve(sbuf, a.lv[0]);
     const int64_t* st = a.st;
 
@@ -235,7 +233,7 @@ __global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
             for (int idx = threadIdx.x; idx < s.V; idx += kT) {
                 int j0, j1, j2;
                 dec3(idx, s.m, j0, j1, j2);
-                R.U[idx] = (a.k0 == 0) ? a.src[j0 * st[0] + j1 * st[1] + j2 * st[2]]
+                R.U[idx] = (a.k0 == 0) ? src[j0 * st[0] + j1 * st[1] + j2 * st[2]]
                                        : L.Wk[idx] + (a.Z0 ? a.Z0[idx] : T(0));
             }
         }
@@ -255,7 +253,7 @@ __global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
                 } else {
                     const T c = R.U[idx] - tail_interp<T, false>(R.U, s, t, j0, j1, j2);
                     R.U[idx] = c;
-                    a.dst[j0 * v0 + j1 * v1 + j2 * v2] = c;
+                    dst[j0 * v0 + j1 * v1 + j2 * v2] = c;
                 }
             }
             __syncthreads();
@@ -270,7 +268,7 @@ __global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
                 for (int idx = threadIdx.x; idx < s.Vc; idx += kT) {
                     int j0, j1, j2;
                     dec3(idx, s.mc, j0, j1, j2);
-                    a.dst[j0 * c0 + j1 * c1 + j2 * c2] = R.W[idx];
+                    dst[j0 * c0 + j1 * c1 + j2 * c2] = R.W[idx];
                 }
             }
         }
@@ -283,7 +281,7 @@ __global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
             for (int idx = threadIdx.x; idx < s.Vc; idx += kT) {
                 int j0, j1, j2;
                 dec3(idx, s.mc, j0, j1, j2);
-                R.W[idx] = a.src[j0 * c0 + j1 * c1 + j2 * c2];
+                R.W[idx] = src[j0 * c0 + j1 * c1 + j2 * c2];
             }
         }
         for (int l = a.nlev - 1; l >= 0; l--) {
@@ -295,7 +293,7 @@ __global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
             for (int idx = threadIdx.x; idx < s.V; idx += kT) {
                 int j0, j1, j2;
                 dec3(idx, s.m, j0, j1, j2);
-                R.U[idx] = (((j0 | j1 | j2) & 1) == 0) ? T(0) : a.src[j0 * v0 + j1 * v1 + j2 * v2];
+                R.U[idx] = (((j0 | j1 | j2) & 1) == 0) ? T(0) : src[j0 * v0 + j1 * v1 + j2 * v2];
             }
             __syncthreads();
             lds_load_vector(R.U, R.P1, R.P2, R.F, s, t);
@@ -321,14 +319,50 @@ __global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
             int j0, j1, j2;
             dec3(idx, s.m, j0, j1, j2);
             if (a.k0 == 0)
-                a.dst[j0 * st[0] + j1 * st[1] + j2 * st[2]] = R.U[idx];
+                dst[j0 * st[0] + j1 * st[1] + j2 * st[2]] = R.U[idx];
             else
                 L.Wk[idx] = R.U[idx];
         }
     }
 }
 
+template <typename T, bool kDec>
+__global__ void __launch_bounds__(kT) k_tail(TailArgs<T> a)
+{
+    __shared__ T sbuf[kTailDataElems];
+    __shared__ T stab[kTailTabElems];
+    tail_body<T, kDec>(a, a.src, a.dst, sbuf, stab);
+}
+
+// One workgroup per entry of a batch; arguments in device memory.
+template <typename T, bool kDec>
+__global__ void __launch_bounds__(kT) k_tail_batch(const TailArgs<T>* __restrict__ args, const int* __restrict__ field,
+                                                   const T* const* __restrict__ src, T* const* __restrict__ dst)
+{
+    __shared__ T sbuf[kTailDataElems];
+    __shared__ T stab[kTailTabElems];
+    const int f = field[blockIdx.x];
+    tail_body<T, kDec>(args[blockIdx.x], src[f], dst[f], sbuf, stab);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, const T* const* src, T* const* dst,
+                             int n, bool decompose, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (decompose)
+        hipLaunchKernelGGL((k_tail_batch<T, true>), dim3((unsigned)n), dim3(kT), 0, st, dev_args, field, src, dst);
+    else
+        hipLaunchKernelGGL((k_tail_batch<T, false>), dim3((unsigned)n), dim3(kT), 0, st, dev_args, field, src, dst);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tail_batch<float>(const TailArgs<float>*, const int*, const float* const*, float* const*,
+                                             int, bool, hipStream_t);
+template hipError_t launch_tail_batch<double>(const TailArgs<double>*, const int*, const double* const*,
+                                              double* const*, int, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& a, bool decompose, hipStream_t st)

@@ -1,0 +1,159 @@
+"""Batched decomposition (one launch per wave of work items plus one launch
+for the small coarse levels) against per-field decompositions on the GPU and
+against the CPU oracle.
+
+The batch runs the same device code as the per-field path, with the same
+arithmetic in the same order, so its results are compared bit for bit; a
+few fields are also checked against the FP64 oracle at the usual tolerance
+(max |gpu - oracle| / max |x|: 1e-12 in float64, 2e-5 in float32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2007_04457_amd as mgr
+from paper_2007_04457_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {torch.float64: 1e-12, torch.float32: 2e-5}
+
+MIXED = [
+    # shape, nonuniform
+    ((33, 17, 65), False),
+    ((65, 65, 65), True),
+    ((129, 129), False),
+    ((17, 9, 33), True),
+    ((257,), False),
+    ((9, 9, 9), False),
+    ((513, 257), True),
+    ((5, 5, 9), False),
+    ((129, 33, 65), False),
+    ((1025, 9), True),
+]
+
+
+def make_fields(cases, dtype, seed0):
+    xs, coords = [], []
+    for i, (shape, nu) in enumerate(cases):
+        u, c = synth.sinusoid_field(shape, seed0 + i, nonuniform=nu)
+        xs.append(torch.from_numpy(u).to(dtype).to(DEV))
+        coords.append(c)
+    return xs, coords
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_batch_equals_per_field(dtype):
+    xs, coords = make_fields(MIXED, dtype, 500)
+    plan = mgr.BatchPlan([x.shape for x in xs], dtype, coords)
+    ys = plan.decompose(xs)
+    torch.cuda.synchronize()
+    for i, (x, c) in enumerate(zip(xs, coords)):
+        want = mgr.decompose(x, c)
+        torch.cuda.synchronize()
+        assert torch.equal(ys[i], want), (i, MIXED[i])
+    # and against the oracle on a few fields
+    for i in (1, 3, 6):
+        xd = xs[i].double().cpu().numpy()
+        ref = oracle.decompose(xd, coords[i])
+        err = float(np.max(np.abs(ys[i].double().cpu().numpy() - ref))) / float(np.max(np.abs(xd)))
+        assert err <= TOL[dtype], (i, err)
+    plan.close()
+
+
+def test_batch_repeated_calls_and_levels():
+    """Second call with other inputs and partial level counts; every counter
+    and the queue start from zero again."""
+    cases = [((65, 33, 17), False), ((129, 65), True), ((33, 33, 33), False)]
+    nl = [2, 3, 1]
+    xs, coords = make_fields(cases, torch.float64, 600)
+    plan = mgr.BatchPlan([x.shape for x in xs], torch.float64, coords, nl)
+    for rep in range(2):
+        if rep:
+            xs = [torch.randn_like(x) for x in xs]
+        ys = plan.decompose(xs)
+        torch.cuda.synchronize()
+        for i, x in enumerate(xs):
+            assert torch.equal(ys[i], mgr.decompose(x, coords[i], nl[i])), (rep, i)
+    plan.close()
+
+
+def test_batch_config_and_autotune():
+    xs, coords = make_fields(MIXED[:6], torch.float32, 700)
+    plan = mgr.BatchPlan([x.shape for x in xs], torch.float32, coords)
+    want = [mgr.decompose(x, c) for x, c in zip(xs, coords)]
+    for chunk in (2, 5, 128):
+        plan.set_config(chunk)
+        assert plan.config()[0] == chunk
+        ys = plan.decompose(xs)
+        torch.cuda.synchronize()
+        for i in range(len(xs)):
+            assert torch.equal(ys[i], want[i]), (chunk, i)
+    dsts = [torch.empty_like(x) for x in xs]
+    chunk, launches, items = plan.autotune(xs, dsts, top_k=2)
+    assert chunk in (2, 4, 8, 16, 32, 64, 128) and launches > 1 and items > 0
+    ys = plan.decompose(xs)
+    torch.cuda.synchronize()
+    for i in range(len(xs)):
+        assert torch.equal(ys[i], want[i]), ("tuned", i)
+    with pytest.raises(mgr.MgrError):
+        plan.set_config(1 << 30)
+    plan.close()
+
+
+def test_batch_rejects_in_place_and_bad_shapes():
+    x = torch.zeros(33, 33, device=DEV)
+    plan = mgr.BatchPlan([x.shape], torch.float32)
+    with pytest.raises(mgr.MgrError):
+        mgr._lib.check(mgr._lib.load().mgr_batch_decompose(plan._h, plan._ptrs([x]), plan._ptrs([x]), None))
+    plan.close()
+    with pytest.raises(mgr.MgrError):
+        mgr.BatchPlan([(33, 34)], torch.float32)
+
+
+def test_batch_graph_replay():
+    """The batch captured into a HIP graph: every replay, with eager work
+    and synchronisation between replays, matches the eager per-field
+    result."""
+    xs, coords = make_fields(MIXED[:5], torch.float32, 800)
+    plan = mgr.BatchPlan([x.shape for x in xs], torch.float32, coords)
+    dsts = [torch.empty_like(x) for x in xs]
+    plan.decompose(xs, dsts)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    want = [mgr.decompose(x, c) for x, c in zip(xs, coords)]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for d in dsts:
+            d.zero_()
+        with torch.cuda.graph(g, stream=s):
+            plan.decompose(xs, dsts)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for d in dsts:
+            d.fill_(float(rep + 7))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        for i in range(len(xs)):
+            assert torch.equal(dsts[i], want[i]), (rep, i)
+        _ = [mgr.decompose(x, c) for x, c in zip(xs, coords)]  # eager work between replays
+    del g
+    plan.close()
+
+
+def test_batch_full_workload_96_fields():
+    """The 96-field float32 workload (80 3-D fields of 2^k+1 per axis, k in
+    [5, 8], and 16 2-D fields, k in [9, 12]) against per-field calls."""
+    shapes = [s for s, _ in synth.batched_shapes()]
+    print(f"\n[batch] {len(shapes)} fields", flush=True)
+    xs = [torch.from_numpy(synth.batched_field(i)).to(torch.float32).to(DEV) for i in range(len(shapes))]
+    plan = mgr.BatchPlan(shapes, torch.float32)
+    ys = plan.decompose(xs)
+    torch.cuda.synchronize()
+    for i, x in enumerate(xs):
+        assert torch.equal(ys[i], mgr.decompose(x)), (i, shapes[i])
+    plan.close()
