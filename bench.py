@@ -202,14 +202,17 @@ def cpu_baseline(u_sin):
 # passes scaled by the same counters on a copy kernel of known size; valid
 # only while the kernel source matches the one the counters were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_dec_513cube_f32_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2007_04457_amd", "csrc", "mgr_stream.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2007_04457_amd", "csrc", f) for f in ("mgr_stream_dev.h", "mgr_stream.hip")]
 
 
 def measured_traffic():
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in KERNEL_SRCS:
+            h.update(open(f, "rb").read())
+        src = h.hexdigest()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha256")))
