@@ -304,6 +304,10 @@ def main():
         "t_decompose_ms": head["t_decompose_ms"], "t_recompose_ms": head["t_recompose_ms"],
         "roundtrip_max_rel_err": head["roundtrip_max_rel_err"],
         "copy_kernel_GBps": round(copy_gbps, 1),
+        # the paper's peak model (Sec. IV-C): achievable single-pass bandwidth
+        # divided by its 8.43 passes per direction
+        "paper_model_peak_GBps": round(copy_gbps / 8.43, 1),
+        "frac_of_paper_model_peak": round(head["GBps"] / (copy_gbps / 8.43), 4),
         "variants": {f"{k[0]}_{k[1]}": v for k, v in results.items()},
     }
     out.update(extra)
