@@ -823,32 +823,23 @@ int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
                 "adjoint copy");
         int rc = solve_all<T>(p, k, true, ws + p.F, st);
         if (rc) return rc;
-        DimTables<T> tb = tables_of<T>(p, k);
-        // t = (M P) y, dimensions first to last; the last pass adds g_f.
-        int npass = 0, done = 0;
-        for (int d = 0; d < 3; d++) npass += p.active[d];
-        int64_t sh[3] = {ly.mc[0], ly.mc[1], ly.mc[2]};
-        const T* in = ws + p.F;
-        View3 iv = packed(sh);
-        View3 gf = level_view(p, k);
-        for (int d = 0; d < 3; d++) {
-            if (!p.active[d]) continue;
-            sh[d] = ly.m[d];
-            bool last = (done == npass - 1);
-            T* out = last ? ws + p.Tb : (npass - 2 - done == 0 ? ws + p.P1 : ws + p.P2);
-            View3 ov = packed(sh);
-            MGR_TRY(timed(KC_MASSTRANS_T, k, st,
-                          [&] { return launch_masstrans_t<T>(in, iv, out, ov, d, tb.K[d], src, gf, last, st); }),
-                    "transposed masstrans launch");
-            in = out;
-            iv = ov;
-            done++;
-        }
-        T* out = (k == 0) ? dst : ws + p.Woff[(size_t)k];
+        // the level-grid output: fine nodes g + (M P) y, coarse nodes G minus
+        // the transposed interpolation of the fine outputs; in place, the
+        // finest step goes through the workspace (its tiles re-read halo
+        // inputs that a neighbouring tile has overwritten)
+        const bool via_tb = (k == 0) && (const void*)src == (const void*)dst;
+        T* out = (k == 0) ? (via_tb ? ws + p.Tb : dst) : ws + p.Woff[(size_t)k];
         View3 ov = (k == 0) ? full_view(p) : packed(ly.m);
-        MGR_TRY(timed(KC_ADJ_COMBINE, k, st,
-                      [&] { return launch_adj_combine<T>(ws + p.Tb, packed(ly.m), out, ov, G, gv, tb, st); }),
-                "adjoint combine launch");
+        MGR_TRY(timed(KC_ADJOINT, k, st,
+                      [&] {
+                          return launch_stream_adjoint<T>(src, level_view(p, k), ws + p.F, G, gv, out, ov,
+                                                          tables_of<T>(p, k), st);
+                      }),
+                "adjoint level launch");
+        if (via_tb) {
+            const size_t bytes = (size_t)(p.n[0] * p.n[1] * p.n[2]) * sizeof(T);
+            MGR_TRY(hipMemcpyAsync(dst, ws + p.Tb, bytes, hipMemcpyDeviceToDevice, st), "adjoint copy-out");
+        }
     }
     return MGR_OK;
 }
@@ -880,7 +871,7 @@ int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const in
 
 const char* const kKernelNames[KC_COUNT] = {
     "coef_decompose", "solve", "interp_recompose",
-    "masstrans_t", "adj_combine", "copy_view", "bench_copy", "stream_dec", "stream_load", "tail", "batch"};
+    "adjoint", "copy_view", "bench_copy", "stream_dec", "stream_load", "tail", "batch"};
 
 // ---- batched decomposition (waves of work items, mgr_batch.hip) --------------
 constexpr int kStagesPerLevel = 10;  // stream + up to three solves of up to three phases

@@ -125,6 +125,12 @@ hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, cons
 
 template <typename T>
 hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
+// One adjoint level step (mgr_adjoint.hip): g / gv the input at the level
+// grid's fine nodes, y the solved corrections and G the coarse-node input
+// (packed coarse grid yv), O / ov the level-grid output (not overlapping g).
+template <typename T>
+hipError_t launch_stream_adjoint(const T* g, View3 gv, const T* y, const T* G, View3 yv, T* O, View3 ov,
+                                 DimTables<T> tb, hipStream_t st);
 // Coarse rows and columns per streaming tile (act1: the problem has a
 // second active dimension); workgroup id = (chunk * nt1 + t1) * nt2 + t2.
 void level_tiling(bool act1, int* kT1, int* kT2);
@@ -197,8 +203,7 @@ enum KernelClass {
     KC_COEF = 0,
     KC_SOLVE,
     KC_INTERP,
-    KC_MASSTRANS_T,
-    KC_ADJ_COMBINE,
+    KC_ADJOINT,
     KC_COPY_VIEW,
     KC_BENCH_COPY,
     KC_STREAM_DEC,
@@ -211,12 +216,6 @@ enum KernelClass {
 template <typename T>
 hipError_t launch_coef_decompose(const T* A, View3 av, T* C, View3 cv, T* W, View3 wv,
                                  DimTables<T> tb, hipStream_t st);
-template <typename T>
-hipError_t launch_masstrans_t(const T* Y, View3 yv, T* X, View3 xv, int d, const T* K,
-                              const T* add, View3 addv, int use_add, hipStream_t st);
-template <typename T>
-hipError_t launch_adj_combine(const T* Tb, View3 tv, T* Out, View3 ov, const T* G,
-                              View3 gv, DimTables<T> tb, hipStream_t st);
 template <typename T>
 hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hipStream_t st);
 

@@ -111,74 +111,6 @@ k_coef_decompose(const T* A, View3 av, T* C, View3 cv,  // A and C may alias (in
     }
 }
 
-// Transposed load-vector stencil along d: X(.., j, ..) = sum_i K_i[j-2i] Y(.., i, ..)
-// (the operator M P of the adjoint).  With use_add the addend is added at
-// fine-only nodes of the output grid.
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_masstrans_t(const T* __restrict__ Y, View3 yv, T* __restrict__ X, View3 xv, int d,
-              const T* __restrict__ K, const T* __restrict__ add, View3 addv, int use_add,
-              int64_t total)
-{
-    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kBlock) {
-        int64_t j[3];
-        decode3(idx, xv.n, j);
-        const int64_t jd = j[d], mc = yv.n[d];
-        int64_t q[3] = {j[0], j[1], j[2]};
-        T s = T(0);
-        const int64_t i0 = (jd >> 1) - 1;
-#pragma unroll
-        for (int r = 0; r < 3; r++) {
-            int64_t i = i0 + r;
-            int64_t t = jd - 2 * i;
-            if (i < 0 || i >= mc || t < -2 || t > 2) continue;
-            q[d] = i;
-            s += K[5 * i + t + 2] * Y[at(yv, q[0], q[1], q[2])];
-        }
-        if (use_add && ((j[0] | j[1] | j[2]) & 1)) s += add[at(addv, j[0], j[1], j[2])];
-        X[at(xv, j[0], j[1], j[2])] = s;
-    }
-}
-
-// Last stage of the adjoint level step: fine-only nodes take Tb (already
-// g_f + M P y), coarse nodes G - Pi^T Tb (gather of the transposed
-// interpolation from the up to 26 fine neighbours).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_adj_combine(const T* __restrict__ Tb, View3 tv, T* __restrict__ Out, View3 ov,
-              const T* __restrict__ G, View3 gv, DimTables<T> tb, int64_t total)
-{
-    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * kBlock) {
-        int64_t j[3];
-        decode3(idx, tv.n, j);
-        if ((j[0] | j[1] | j[2]) & 1) {
-            Out[at(ov, j[0], j[1], j[2])] = Tb[at(tv, j[0], j[1], j[2])];
-            continue;
-        }
-        T s = T(0);
-        for (int a = -1; a <= 1; a++) {
-            int64_t p0 = j[0] + a;
-            if (p0 < 0 || p0 >= tv.n[0]) continue;
-            T w0 = (a == 0) ? T(1) : (a > 0 ? tb.w[0][2 * p0] : tb.w[0][2 * p0 + 1]);
-            for (int b = -1; b <= 1; b++) {
-                int64_t p1 = j[1] + b;
-                if (p1 < 0 || p1 >= tv.n[1]) continue;
-                T w1 = (b == 0) ? T(1) : (b > 0 ? tb.w[1][2 * p1] : tb.w[1][2 * p1 + 1]);
-                for (int c = -1; c <= 1; c++) {
-                    int64_t p2 = j[2] + c;
-                    if (p2 < 0 || p2 >= tv.n[2]) continue;
-                    if (a == 0 && b == 0 && c == 0) continue;
-                    T w2 = (c == 0) ? T(1) : (c > 0 ? tb.w[2][2 * p2] : tb.w[2][2 * p2 + 1]);
-                    s += w0 * w1 * w2 * Tb[at(tv, p0, p1, p2)];
-                }
-            }
-        }
-        Out[at(ov, j[0], j[1], j[2])] = G[at(gv, j[0] >> 1, j[1] >> 1, j[2] >> 1)] - s;
-    }
-}
-
 // Y = X (+ Z, with Z laid out like X when given): gathers and scatters of
 // the coarsest grid between the caller's array and the workspace.
 template <typename T>
@@ -218,26 +150,6 @@ hipError_t launch_coef_decompose(const T* A, View3 av, T* C, View3 cv, T* W, Vie
 }
 
 template <typename T>
-hipError_t launch_masstrans_t(const T* Y, View3 yv, T* X, View3 xv, int d, const T* K,
-                              const T* add, View3 addv, int use_add, hipStream_t st)
-{
-    int64_t total = vol(xv);
-    hipLaunchKernelGGL(k_masstrans_t<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, Y, yv, X,
-                       xv, d, K, add, addv, use_add, total);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_adj_combine(const T* Tb, View3 tv, T* Out, View3 ov, const T* G,
-                              View3 gv, DimTables<T> tb, hipStream_t st)
-{
-    int64_t total = vol(tv);
-    hipLaunchKernelGGL(k_adj_combine<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, Tb, tv,
-                       Out, ov, G, gv, tb, total);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hipStream_t st)
 {
     int64_t total = vol(yv);
@@ -257,10 +169,6 @@ hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStrea
 #define MGR_INSTANTIATE(T)                                                                      \
     template hipError_t launch_coef_decompose<T>(const T*, View3, T*, View3, T*, View3,         \
                                                  DimTables<T>, hipStream_t);                    \
-    template hipError_t launch_masstrans_t<T>(const T*, View3, T*, View3, int, const T*,        \
-                                              const T*, View3, int, hipStream_t);               \
-    template hipError_t launch_adj_combine<T>(const T*, View3, T*, View3, const T*, View3,      \
-                                              DimTables<T>, hipStream_t);                       \
     template hipError_t launch_copy_view<T>(const T*, const T*, View3, T*, View3, hipStream_t);
 
 MGR_INSTANTIATE(float)
