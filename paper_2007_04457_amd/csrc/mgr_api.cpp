@@ -941,7 +941,7 @@ int batch_tables(BatchPlan& b, int chunk, BatchTables<T>& out)
             a.write_coarse = (k == 0) ? 1 : 0;
             const bool act0 = a.av.n[0] > 1, act1 = a.av.n[1] > 1;
             int kT1, kT2;
-            level_tiling(act1, &kT1, &kT2);
+            level_tiling(act1, (int)sizeof(T), &kT1, &kT2);
             a.nt1 = act1 ? (int)cdiv(a.fv.n[1], kT1) : 1;
             a.nt2 = (int)cdiv(a.fv.n[2], kT2);
             const int c0 = (int)a.fv.n[0];
@@ -1231,7 +1231,7 @@ double batch_model_us(const BatchPlan& b, int chunk)
             const double c0 = (double)ly.mc[0];
             const bool act0 = ly.m[0] > 1, act1 = ly.m[1] > 1;
             int kT1, kT2;
-            level_tiling(act1, &kT1, &kT2);
+            level_tiling(act1, (int)esz, &kT1, &kT2);
             const double tiles = (act1 ? std::ceil((double)ly.mc[1] / kT1) : 1.0) * std::ceil((double)ly.mc[2] / kT2);
             const double ch = act0 ? std::min<double>(std::max(chunk, 2), c0) : c0;
             const double nch = act0 ? std::ceil(c0 / ch) : 1.0;

@@ -55,10 +55,21 @@ __device__ __attribute__((noinline)) void exec_stream(const BatchKernelArgs<T>* 
     StreamArgs<T> a = load_uniform(A->sargs + it.args);
     if (!a.A) a.A = load_uniform(A->src + it.field);
     a.C = load_uniform(A->dst + it.field);
+    // unit column strides: FP32 column pairs move in single 8-byte accesses
+    const bool unit = a.av.s[2] == 1 && a.cv.s[2] == 1;
+    if constexpr (cols_per_lane<T>() == 2) {
+        if (unit) {
+            if (a.Z)
+                stream_level_tile<T, kAct0, kAct1, true, true, true>(a, it.bx, sm);
+            else
+                stream_level_tile<T, kAct0, kAct1, true, false, true>(a, it.bx, sm);
+            return;
+        }
+    }
     if (a.Z)
-        stream_level_tile<T, kAct0, kAct1, true, true>(a, it.bx, sm);
+        stream_level_tile<T, kAct0, kAct1, true, true, false>(a, it.bx, sm);
     else
-        stream_level_tile<T, kAct0, kAct1, true, false>(a, it.bx, sm);
+        stream_level_tile<T, kAct0, kAct1, true, false, false>(a, it.bx, sm);
 }
 
 template <typename T>

@@ -132,8 +132,9 @@ template <typename T>
 hipError_t launch_stream_adjoint(const T* g, View3 gv, const T* y, const T* G, View3 yv, T* O, View3 ov,
                                  DimTables<T> tb, hipStream_t st);
 // Coarse rows and columns per streaming tile (act1: the problem has a
-// second active dimension); workgroup id = (chunk * nt1 + t1) * nt2 + t2.
-void level_tiling(bool act1, int* kT1, int* kT2);
+// second active dimension; elem_bytes: 4 or 8); workgroup id =
+// (chunk * nt1 + t1) * nt2 + t2.
+void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2);
 template <typename T>
 hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st);
 

@@ -24,6 +24,8 @@
 // take (row, segment) pairs.  Separators are solved in LDS by one lane per
 // fibre.  Longer fibres fall back to three launches (segment ends,
 // separators, final) through global memory.
+#include <algorithm>
+
 #include "mgr_solve_dev.h"
 
 namespace mgr {
@@ -43,17 +45,14 @@ k_solve_strided_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb)
 // A block takes whole rows (rows_per_block * S lanes); their data are one
 // contiguous span of F, staged through LDS with one pad element per 32 so
 // that each lane's segment reads are bank-conflict free.
-// A block takes whole rows (rows_per_block * S lanes); their data are one
-// contiguous span of F, staged through LDS with one pad element per 32 so
-// that each lane's segment reads are bank-conflict free.
 template <typename T, bool kLdsTab>
 __global__ void __launch_bounds__(kBlk)
 k_solve_rows_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb, int rows_per_block)
 {
-    __shared__ RowsSmem<T, kSpanMax, kLdsTab> sm;
+    __shared__ RowsSmem<T, rows_span<T>(), kLdsTab> sm;
     const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
     const int nrows = (int)min((int64_t)rows_per_block, m.nfib - row0);
-    solve_rows_tile<T, kSpanMax, kLdsTab>(F, m, tb, row0, nrows, sm);
+    solve_rows_tile<T, rows_span<T>(), kLdsTab>(F, m, tb, row0, nrows, sm);
 }
 
 template <typename T>
@@ -93,8 +92,11 @@ hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T*
     for (int e = 0; e < d; e++) m.outer *= fv.n[e];
     m.nfib = m.inner * m.outer;
     m.S = tb.S;
-    if (m.inner == 1 && m.S <= kBlk) {
-        const int rpb = kBlk / m.S;
+    if (m.inner == 1 && m.S <= kBlk && m.n <= rows_span<T>()) {
+        // rows per block: as many as fit, but at most an even share of two
+        // workgroups per CU, so that small levels still spread over the chip
+        const int64_t share = (m.nfib + 2 * (int64_t)device_cu_count() - 1) / (2 * (int64_t)device_cu_count());
+        const int rpb = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(kBlk / m.S), (int64_t)(rows_span<T>() / m.n), share}));
         const unsigned nb = (unsigned)((m.nfib + rpb - 1) / rpb);
         if (m.S <= kMaxSegWG)
             hipLaunchKernelGGL((k_solve_rows_wg<T, true>), dim3(nb), dim3(kBlk), 0, st, F, m, tb, rpb);

@@ -139,6 +139,13 @@ __device__ __forceinline__ void solve_strided_tile(T* __restrict__ F, const Fibr
 // ---- contiguous dimension, one launch --------------------------------------
 // ---- contiguous dimension: rows staged through LDS ------------------------
 constexpr int kSpanMax = kBlk * kSlot;
+// Elements a per-level rows workgroup stages: the same bytes for either type
+// (FP64 stages half the elements), so both keep three workgroups per CU.
+template <typename T>
+constexpr int rows_span()
+{
+    return kSpanMax * 4 / (int)sizeof(T);
+}
 __device__ __forceinline__ int padded(int e) { return e + (e >> 5); }
 
 template <typename T, int kSpan, bool kLdsTab>
@@ -146,6 +153,7 @@ struct RowsSmem {
     T f[kSpan + kSpan / 32 + 1];
     T end[2][kBlk];
     T tab[5][kLdsTab ? kMaxSegWG * kSlot : 1];  // segment tables (S <= kMaxSegWG)
+    T septab[5][kLdsTab ? kMaxSegWG : kBlk];    // sub, sup, sl, sip, su at separators
 };
 
 // Rows row0 .. row0 + nrows - 1 (nrows * S <= kBlk, nrows * n <= kSpan).
@@ -157,7 +165,20 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
     const int n = (int)m.n;
     const int span = nrows * n;
     T* g = F + row0 * n;
-    for (int e = threadIdx.x; e < span; e += kBlk) sm.f[padded(e)] = g[e];
+    // every load of the span issued before the first LDS write, so that they
+    // are all in flight together (indices clamped into the span: the loads
+    // are unconditional)
+    {
+        constexpr int kLoads = (kSpan + kBlk - 1) / kBlk;
+        T tmp[kLoads];
+#pragma unroll
+        for (int q = 0; q < kLoads; q++) tmp[q] = g[min(q * kBlk + (int)threadIdx.x, span - 1)];
+#pragma unroll
+        for (int q = 0; q < kLoads; q++) {
+            const int e = q * kBlk + (int)threadIdx.x;
+            if (e < span) sm.f[padded(e)] = tmp[q];
+        }
+    }
     if (kLdsTab)
         for (int e = threadIdx.x; e < m.S * kSlot; e += kBlk) {
             sm.tab[0][e] = tb.L[e];
@@ -166,6 +187,15 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
             sm.tab[3][e] = tb.A[e];
             sm.tab[4][e] = tb.B[e];
         }
+    // separator tables: the separator sweep below is serial, so each of its
+    // steps must find them in LDS rather than wait on a global load
+    for (int e = threadIdx.x; e < m.S; e += kBlk) {
+        sm.septab[0][e] = tb.ssub[e];
+        sm.septab[1][e] = tb.ssup[e];
+        sm.septab[2][e] = tb.sl[e];
+        sm.septab[3][e] = tb.sip[e];
+        sm.septab[4][e] = tb.su[e];
+    }
     const int r = threadIdx.x / m.S, s = threadIdx.x % m.S;
     const bool active = r < nrows;
     const int rr = active ? r : 0;
@@ -191,14 +221,14 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
         T gg = T(0);
         for (int k = 1; k < m.S; k++) {
             const int e = padded(r * n + k * kSeg);
-            const T rhs = sm.f[e] - tb.ssub[k] * sm.end[1][t0 + k - 1] - tb.ssup[k] * sm.end[0][t0 + k];
-            gg = (k == 1) ? rhs : rhs - tb.sl[k] * gg;
+            const T rhs = sm.f[e] - sm.septab[0][k] * sm.end[1][t0 + k - 1] - sm.septab[1][k] * sm.end[0][t0 + k];
+            gg = (k == 1) ? rhs : rhs - sm.septab[2][k] * gg;
             sm.f[e] = gg;
         }
         T z = T(0);
         for (int k = m.S - 1; k >= 1; k--) {
             const int e = padded(r * n + k * kSeg);
-            z = (k == m.S - 1) ? sm.f[e] * tb.sip[k] : (sm.f[e] - tb.su[k] * z) * tb.sip[k];
+            z = (k == m.S - 1) ? sm.f[e] * sm.septab[3][k] : (sm.f[e] - sm.septab[4][k] * z) * sm.septab[3][k];
             sm.f[e] = z;
         }
     }

@@ -30,11 +30,12 @@
 namespace mgr {
 namespace {
 
-template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ>
-__global__ void __launch_bounds__(kThreads) k_stream_level(StreamArgs<T> a)
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(stream_min_waves<T, kDec, kZ>(), 8)))
+k_stream_level(StreamArgs<T> a)
 {
     __shared__ LevelSmem<T, kAct0, kAct1, kDec> sm;
-    stream_level_tile<T, kAct0, kAct1, kDec, kZ>(a, remap_xcd((int)blockIdx.x, (int)gridDim.x), sm);
+    stream_level_tile<T, kAct0, kAct1, kDec, kZ, kU>(a, remap_xcd((int)blockIdx.x, (int)gridDim.x), sm);
 }
 
 // Recomposition of one level step (Sec. II-A, the inverse of the above):
@@ -238,15 +239,15 @@ int resident_per_cu(K kern, int& cache)
     return cache;
 }
 
-template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ>
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
 hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st)
 {
-    using G = LevelGeom<kAct1>;
+    using G = LevelGeom<kAct1, cols_per_lane<T>()>;
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
     a.nt1 = kAct1 ? (c1 + G::kT1 - 1) / G::kT1 : 1;
     a.nt2 = (c2 + G::kT2 - 1) / G::kT2;
     const int tiles = a.nt1 * a.nt2;
-    auto kern = k_stream_level<T, kAct0, kAct1, kDec, kZ>;
+    auto kern = k_stream_level<T, kAct0, kAct1, kDec, kZ, kU>;
     int chunk = c0;
     if (kAct0) {
         // One round of resident workgroups: a second, partial round would
@@ -263,12 +264,23 @@ hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename T, bool kAct0, bool kAct1, bool kU>
+hipError_t launch_cfg_u(StreamArgs<T> a, bool dec, hipStream_t st)
+{
+    if (dec && a.Z) return launch_level_cfg<T, kAct0, kAct1, true, true, kU>(a, st);
+    if (dec) return launch_level_cfg<T, kAct0, kAct1, true, false, kU>(a, st);
+    return launch_level_cfg<T, kAct0, kAct1, false, false, kU>(a, st);
+}
+
 template <typename T, bool kAct0, bool kAct1>
 hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
 {
-    if (dec && a.Z) return launch_level_cfg<T, kAct0, kAct1, true, true>(a, st);
-    if (dec) return launch_level_cfg<T, kAct0, kAct1, true, false>(a, st);
-    return launch_level_cfg<T, kAct0, kAct1, false, false>(a, st);
+    // unit column stride of the input and (decomposing) of the coefficients:
+    // FP32 column pairs then move in single 8-byte accesses
+    const bool unit = a.av.s[2] == 1 && (!dec || a.cv.s[2] == 1);
+    if constexpr (cols_per_lane<T>() == 2)
+        if (unit) return launch_cfg_u<T, kAct0, kAct1, true>(a, dec, st);
+    return launch_cfg_u<T, kAct0, kAct1, false>(a, dec, st);
 }
 
 template <typename T, bool kAct0, bool kAct1>
@@ -308,10 +320,16 @@ hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
-void level_tiling(bool act1, int* kT1, int* kT2)
+void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2)
 {
-    *kT1 = act1 ? LevelGeom<true>::kT1 : LevelGeom<false>::kT1;
-    *kT2 = act1 ? LevelGeom<true>::kT2 : LevelGeom<false>::kT2;
+    constexpr int Cf = cols_per_lane<float>(), Cd = cols_per_lane<double>();
+    if (elem_bytes == 4) {
+        *kT1 = act1 ? LevelGeom<true, Cf>::kT1 : LevelGeom<false, Cf>::kT1;
+        *kT2 = act1 ? LevelGeom<true, Cf>::kT2 : LevelGeom<false, Cf>::kT2;
+    } else {
+        *kT1 = act1 ? LevelGeom<true, Cd>::kT1 : LevelGeom<false, Cd>::kT1;
+        *kT2 = act1 ? LevelGeom<true, Cd>::kT2 : LevelGeom<false, Cd>::kT2;
+    }
 }
 
 template <typename T>

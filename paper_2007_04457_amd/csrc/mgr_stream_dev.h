@@ -22,6 +22,14 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Five-term dot product with a fixed association and rounding (an explicit
+// FMA chain), so that every kernel that inlines it rounds identically.
+template <typename T>
+__device__ __forceinline__ T dot5(T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3, T a4, T b4)
+{
+    return fma(a4, b4, fma(a3, b3, fma(a2, b2, fma(a1, b1, a0 * b0))));
+}
+
 // Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber so
 // each XCD works on a contiguous range of tiles and neighbouring tiles share
 // its L2 for the halo re-reads.
@@ -33,29 +41,61 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
     return (x < rem) ? x * (lo + 1) + local : rem * (lo + 1) + (x - rem) * lo + local;
 }
 
-// Geometry of the streaming level kernel, per problem dimensionality.
-//  3-D: a workgroup owns kT1 = 8 coarse rows x kT2 = 30 coarse columns; its
-//       staged region is 19 fine rows x 64 columns (63 used), one wave per
-//       row (rows r = wave, wave + 4, ...), lane = column.
-//  2-D (m0, 1, m2) and 1-D (1, 1, m2): one staged row of 256 columns (255
-//       used), four waves side by side; kT2 = 126 coarse columns.
-template <bool kAct1>
+// Geometry of the streaming level kernel, per problem dimensionality and
+// element size.  A lane owns CPL = 8 / sizeof(T) consecutive staged columns
+// (a column pair in FP32, one column in FP64), so that every global access of
+// a lane moves 8 bytes.
+//  3-D: a workgroup owns kT1 = 8 coarse rows x kT2 coarse columns (62 in
+//       FP32, 30 in FP64); its staged region is 19 fine rows x 2 kT2 + 3
+//       columns, one wave per row (rows r = wave, wave + 4, ...).
+//  2-D (m0, 1, m2) and 1-D (1, 1, m2): one staged row, four waves side by
+//       side (kT2 = 254 in FP32, 126 in FP64).
+template <bool kAct1, int CPL>
 struct LevelGeom {
-    static constexpr int kT1 = kAct1 ? 8 : 1;
-    static constexpr int kT2 = kAct1 ? 30 : 126;
-    static constexpr int NR = kAct1 ? 2 * kT1 + 3 : 1;  // staged rows
     static constexpr int CW = kAct1 ? 1 : 4;            // waves per staged row
-    static constexpr int NCW = 64 * CW;                 // staged columns
+    static constexpr int NL = 64 * CW;                  // lanes per staged row
+    static constexpr int NCW = CPL * NL;                // staged columns
+    static constexpr int kT1 = kAct1 ? 8 : 1;
+    static constexpr int kT2 = (NCW - 3) / 2;
+    static constexpr int NR = kAct1 ? 2 * kT1 + 3 : 1;  // staged rows
     static constexpr int RW = 4 / CW;                   // rows handled at once
     static constexpr int NRW = (NR + RW - 1) / RW;      // rows per wave
     static constexpr int H = NCW / 2;                   // even (odd) columns per row
-    static constexpr int GW = kAct1 ? 32 : 256;         // dim-2 outputs per pass row
+    static constexpr int GW = kAct1 ? 32 * CPL : 256;   // dim-2 outputs per pass row
     static constexpr int OB = NR * H + 16;              // odd-column block (bank offset 16)
     static_assert(2 * kT2 + 3 <= NCW, "region fits the staged width");
     static_assert(kT2 + 2 <= H && kT2 <= GW, "stencil windows fit");
 };
+// One column per lane for both types.  FP32 column pairs (CPL = 2, one
+// 8-byte access per lane) are supported by the code but not used: rows of
+// 2^k + 1 elements start at odd element offsets on every other row, and an
+// 8-byte buffer access at a 4-byte-aligned address is not performed as an
+// unaligned access on this device, so half of the rows would need two
+// accesses; measured, the pair layout was slower.
+template <typename T>
+constexpr int cols_per_lane()
+{
+    return 1;
+}
 
 constexpr int kMaxChunk = 128;       // coarse planes per workgroup (LDS tables)
+// Plane buffers of the streaming tile (its prefetch depth plus one): four
+// for the FP32 decomposition pass without a correction array, two where the
+// registers are needed elsewhere (FP64, the correction's second array, or
+// the load-vector pass, which runs at higher occupancy).
+template <typename T, bool kDec, bool kZ>
+constexpr int stream_ring()
+{
+    return (sizeof(T) == 4 && kDec && !kZ) ? 4 : 2;
+}
+// Minimum waves per SIMD the streaming kernel is compiled for: the deep ring
+// is held at five (at most 96 registers, a few spilled), which measured
+// faster than four waves without spills.
+template <typename T, bool kDec, bool kZ>
+constexpr int stream_min_waves()
+{
+    return stream_ring<T, kDec, kZ>() == 4 ? 5 : 1;
+}
 constexpr unsigned kOut = 0x80000000u;  // buffer offset past every range: loads 0, stores dropped
 
 // Marks a value the same in every lane (kept in scalar registers).
@@ -99,10 +139,45 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uns
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
 {
-    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+// A lane's CPL consecutive columns of one row.  FP32 pairs move as one
+// 8-byte access where the columns are adjacent in memory (kU), else as two
+// 4-byte accesses `step` bytes apart.  The hardware range check is per
+// dword, so a pair that straddles the end of a row keeps its first element.
+template <bool kU, typename T, int N>
+__device__ __forceinline__ void buf_load_cols(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned step, T (&v)[N])
+{
+    static_assert(N == 1 || (N == 2 && sizeof(T) == 4), "one column, or an FP32 pair");
+    if constexpr (N == 1) {
+        v[0] = buf_load<T>(r, off);
+    } else if (kU) {
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        v[0] = __builtin_bit_cast(T, w.x);
+        v[1] = __builtin_bit_cast(T, w.y);
+    } else {
+        v[0] = buf_load<T>(r, off);
+        v[1] = buf_load<T>(r, off + step);
+    }
+}
+template <bool kU, typename T, int N>
+__device__ __forceinline__ void buf_store_cols(const T (&v)[N], __amdgpu_buffer_rsrc_t r, unsigned off, unsigned step)
+{
+    static_assert(N == 1 || (N == 2 && sizeof(T) == 4), "one column, or an FP32 pair");
+    if constexpr (N == 1) {
+        buf_store(v[0], r, off);
+    } else if (kU) {
+        u32x2 w;
+        w.x = __builtin_bit_cast(unsigned, v[0]);
+        w.y = __builtin_bit_cast(unsigned, v[1]);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+    } else {
+        buf_store(v[0], r, off);
+        buf_store(v[1], r, off + step);
+    }
 }
 
 // LDS of one streaming level tile.  sU: the staged plane (even planes); sC:
@@ -111,8 +186,8 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
 // results [r][GW]; sW0, sK0: dim-0 interpolation weights and stencil rows of
 // the chunk.
 template <typename T, bool kAct0, bool kAct1, bool kDec>
-struct LevelSmem {
-    using G = LevelGeom<kAct1>;
+struct alignas(16) LevelSmem {
+    using G = LevelGeom<kAct1, cols_per_lane<T>()>;
     T sU[kDec ? G::NR * G::NCW : 1];
     T sC[G::OB + G::NR * G::H];
     T sG[G::NR * G::GW];
@@ -122,16 +197,22 @@ struct LevelSmem {
 
 // One workgroup's share of a level step: tile (t1, t2) of coarse columns and
 // chunk ch of coarse planes, bid = (ch * nt1 + t1) * nt2 + t2.  Used by the
-// per-level launch below and by the batched work-queue kernel.
-template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ>
+// per-level launch and by the batched kernel.  kU: the input (and, when
+// decomposing, the coefficient output) has unit column stride, so a lane's
+// columns move in one access.
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
 __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bid,
                                                   LevelSmem<T, kAct0, kAct1, kDec>& sm)
 {
-    using G = LevelGeom<kAct1>;
+    constexpr int CPL = cols_per_lane<T>();
+    using G = LevelGeom<kAct1, CPL>;
     constexpr int NR = G::NR, NCW = G::NCW, NRW = G::NRW, RW = G::RW, H = G::H, GW = G::GW;
     constexpr int kT1 = G::kT1, kT2 = G::kT2, OB = G::OB;
     constexpr int NGP = (NR + (kThreads / GW) - 1) / (kThreads / GW);  // dim-2 passes
+    constexpr int NOUT = kAct1 ? kT1 / (kThreads / GW) : 1;            // dim-1 outputs per thread
+    constexpr bool kRowUni = (GW == 64);  // a dim-2 pass row (and dim-1 output row) per wave
     constexpr unsigned S = sizeof(T);
+    static_assert(!kAct1 || NOUT * (kThreads / GW) == kT1, "dim-1 outputs cover the tile");
     T* const sU = sm.sU;
     T* const sC = sm.sC;
     T* const sG = sm.sG;
@@ -151,7 +232,6 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     const int P0 = ch * a.chunk, P1 = min(P0 + a.chunk, c0);
     const int R0 = kAct1 ? 2 * I1 - 2 : 0;  // region origin (may be negative)
     const int C0 = 2 * I2 - 2;
-    const int RB = max(R0, 0);              // first in-grid region row
     const int F0 = kAct0 ? max(2 * P0 - 2, 0) : 0;
     const int F1 = kAct0 ? min(2 * P1, m0 - 1) : 0;
     const int oF0 = kAct0 ? 2 * P0 : 0, oF1 = kAct0 ? min(2 * P1, m0) : 1;
@@ -166,67 +246,109 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
             sK0[e] = (i >= P0 && i < P1) ? a.tb.K[0][5 * i + e % 5] : T(0);
         }
 
-    // ---- this lane's staged column
-    const int c = (wave % G::CW) * 64 + lane;
-    const int gc = C0 + c;
-    const bool cin = c < 2 * kT2 + 3 && gc >= 0 && gc < m2;
-    const bool cown = cin && gc >= 2 * I2 && gc < min(2 * (I2 + kT2), m2);
-    const bool ceven = !(c & 1);
-    // interpolation weights: zero outside the grid, so outside nodes get a
-    // zero coefficient (their loads return zero); (1, 0) at even columns, so
-    // coarse nodes get exactly u - u = 0
-    T wcl = T(0), wch = T(0);
-    int ucl = 0, ucr = 0;
-    if (kDec && cin) {
-        ucl = c & ~1;
-        ucr = ucl + 2 * (c & 1);
-        wcl = (c & 1) ? a.tb.w[2][2 * gc] : T(1);
-        wch = (c & 1) ? a.tb.w[2][2 * gc + 1] : T(0);
+    // ---- this lane's staged columns cb .. cb + CPL - 1
+    const int cb = ((wave % G::CW) * 64 + lane) * CPL;
+    const int gc = C0 + cb;  // global column of cb
+    constexpr int RC = 2 * kT2 + 3;  // region columns
+    // column j of the lane: in the region and the grid / owned by the tile
+    auto col_in = [&](int j) { return cb + j < RC && gc + j >= 0 && gc + j < m2; };
+    auto col_own = [&](int j) { return col_in(j) && gc + j >= 2 * I2 && gc + j < min(2 * (I2 + kT2), m2); };
+    // Interpolation weights per column: zero outside the grid, so outside
+    // nodes get a zero coefficient (their loads return zero); (1, 0) at even
+    // columns, so coarse nodes get exactly u - u = 0.  ul, ur: staged columns
+    // of the two coarse neighbours (the column itself at even columns).
+    T wcl[CPL], wch[CPL];
+    int ul[CPL], ur[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; j++) {
+        const int cj = cb + j;
+        const bool odd = cj & 1;
+        wcl[j] = wch[j] = T(0);
+        ul[j] = ur[j] = cb;
+        if (kDec && col_in(j)) {
+            ul[j] = cj & ~1;
+            ur[j] = odd ? cj + 1 : cj & ~1;
+            wcl[j] = odd ? a.tb.w[2][2 * (gc + j)] : T(1);
+            wch[j] = odd ? a.tb.w[2][2 * (gc + j) + 1] : T(0);
+        }
     }
-    // ---- this wave's staged rows r = rg + RW * k (wave-uniform)
-    const int rg = wave / G::CW;
-    T* const sUw = sU + rg * NCW + c;
-    const T* const sUl = sU + rg * NCW + ucl;
-    const T* const sUr = sU + rg * NCW + ucr;
-    T* const sCw = sC + rg * H + (c & 1) * OB + (c >> 1);
+    // byte offsets of the lane's first column, per array (kOut: no column
+    // of the lane in range); the pair's second column is `step` bytes on
+    bool any_in = false, any_own = false;
+#pragma unroll
+    for (int j = 0; j < CPL; j++) {
+        any_in = any_in || col_in(j);
+        any_own = any_own || col_own(j);
+    }
     const int as1 = (int)a.av.s[1], as2 = (int)a.av.s[2];
     const int cs1 = (int)a.cv.s[1], cs2 = (int)a.cv.s[2];
     const int ws1 = (int)a.wv.s[1], ws2 = (int)a.wv.s[2];
+    // the coarse value goes to W from the lane's column 0 (even in FP32, where
+    // cb is even; in FP64 only at even lanes)
+    constexpr int jw = 0;
+    const bool w_own = col_own(jw) && !((cb + jw) & 1);
+    const unsigned cA = any_in ? (unsigned)(gc * as2) * S : kOut;
+    const unsigned cC = any_own ? (unsigned)(gc * cs2) * S : kOut;
+    const unsigned cW = w_own ? (unsigned)(((gc + jw) >> 1) * ws2) * S : kOut;
+    const unsigned stepA = (unsigned)as2 * S, stepC = (unsigned)cs2 * S;
+
+    // ---- this wave's staged rows r = rg + RW * k (wave-uniform)
+    const int rg = wave / G::CW;
+    T* const sUw = sU + rg * NCW + cb;
+    const T* const sUrow = sU + rg * NCW;
+    T* const sCrow = sC + rg * H;
     const int oR0 = kAct1 ? 2 * I1 : 0, oR1 = kAct1 ? min(2 * (I1 + kT1), m1) : 1;
-    unsigned vA[NRW], vC[NRW], vW[NRW];  // byte offsets from the region's first in-grid row
+    // A row's buffer descriptor starts at the row (wave-uniform, scalar) and
+    // holds the row's bytes, or none for a row outside the grid (or not owned,
+    // for the outputs)
+    const unsigned rowA = (unsigned)((m2 - 1) * as2 + 1) * S;
+    const unsigned rowC = (unsigned)((m2 - 1) * cs2 + 1) * S;
+    const unsigned rowW = (unsigned)(((m2 - 1) / 2) * ws2 + 1) * S;
+    int gr[NRW];               // grid row (uniform)
+    bool rin[NRW], rown[NRW];  // in the grid / owned (uniform)
     T wrl[NRW], wrh[NRW];
 #pragma unroll
     for (int k = 0; k < NRW; k++) {
         const int r = rg + RW * k;
-        const int gr = R0 + r;
-        const bool rin = r < NR && gr >= 0 && gr < m1;
-        const bool own = rin && cown && gr >= oR0 && gr < oR1;
-        vA[k] = (rin && cin) ? (unsigned)((gr - RB) * as1 + gc * as2) * S : kOut;
-        vC[k] = own ? (unsigned)((gr - RB) * cs1 + gc * cs2) * S : kOut;
-        vW[k] = (own && !(gr & 1) && ceven) ? (unsigned)(((gr - RB) >> 1) * ws1 + (gc >> 1) * ws2) * S : kOut;
+        gr[k] = R0 + r;
+        rin[k] = r < NR && gr[k] >= 0 && gr[k] < m1;
+        rown[k] = rin[k] && gr[k] >= oR0 && gr[k] < oR1;
         wrl[k] = T(0);
         wrh[k] = T(0);
-        if (kDec && rin) {
-            wrl[k] = (kAct1 && (r & 1)) ? uni(a.tb.w[1][2 * gr]) : T(1);
-            wrh[k] = (kAct1 && (r & 1)) ? uni(a.tb.w[1][2 * gr + 1]) : T(0);
+        if (kDec && rin[k]) {
+            wrl[k] = (kAct1 && (r & 1)) ? uni(a.tb.w[1][2 * gr[k]]) : T(1);
+            wrh[k] = (kAct1 && (r & 1)) ? uni(a.tb.w[1][2 * gr[k] + 1]) : T(0);
         }
     }
-    // bytes reachable from the region's first in-grid row, per array
-    const unsigned spanA = (unsigned)((min(R0 + NR, m1) - RB) * as1 + m2 * as2) * S;
-    const unsigned spanC = (unsigned)((min(R0 + NR, m1) - RB) * cs1 + m2 * cs2) * S;
-    const unsigned spanW = (unsigned)(((min(R0 + NR, m1) - RB) / 2 + 1) * ws1 + ((m2 + 1) / 2) * ws2) * S;
 
-    // ---- dim-2 / dim-1 stencil weights of this thread's output column
-    const int g2 = tid % GW, g1 = tid / GW;  // output: coarse row I1+g1, column I2+g2
-    T k2[5], k1[5];
+    // ---- dim-2 / dim-1 stencil weights of this thread's outputs: coarse
+    // column I2 + g2, coarse rows I1 + g1 + q (kThreads / GW), q < NOUT
+    const int g2 = tid % GW;
+    const int g1 = kRowUni ? wave : tid / GW;
+    T k2[5], k1[NOUT][5];
 #pragma unroll
     for (int t = 0; t < 5; t++) {
         k2[t] = (g2 < kT2 && I2 + g2 < c2) ? a.tb.K[2][5 * (I2 + g2) + t] : T(0);
-        k1[t] = (kAct1 && g1 < kT1 && I1 + g1 < c1) ? a.tb.K[1][5 * (I1 + g1) + t] : T(0);
+#pragma unroll
+        for (int q = 0; q < NOUT; q++) {
+            const int i1 = I1 + g1 + q * (kThreads / GW);
+            const T kv = (kAct1 && i1 < c1) ? a.tb.K[1][5 * i1 + t] : T(0);
+            k1[q][t] = kRowUni ? uni(kv) : kv;
+        }
     }
-    const bool gvalid = g1 < kT1 && g2 < kT2 && I1 + g1 < c1 && I2 + g2 < c2;
-    const unsigned vF = gvalid ? (unsigned)((I1 + g1) * (int)a.fv.s[1] + (I2 + g2) * (int)a.fv.s[2]) * S : kOut;
-    const unsigned spanF = (unsigned)((c1 - 1) * (int)a.fv.s[1] + c2 * (int)a.fv.s[2]) * S;
+    // load-vector outputs: with one output row per wave the row goes into
+    // the (scalar) descriptor, else into the lane's offset
+    const bool cvalid = g2 < kT2 && I2 + g2 < c2;
+    const int fs1 = (int)a.fv.s[1], fs2 = (int)a.fv.s[2];
+    const unsigned rowF = (unsigned)((c2 - 1) * fs2 + 1) * S;
+    const unsigned spanF = (unsigned)((c1 - 1) * fs1 + (c2 - 1) * fs2 + 1) * S;
+    unsigned vF[NOUT];
+#pragma unroll
+    for (int q = 0; q < NOUT; q++) {
+        const int i1 = I1 + g1 + q * (kThreads / GW);
+        const bool ok = cvalid && (!kAct1 || i1 < c1);
+        vF[q] = ok ? (unsigned)((kRowUni ? 0 : i1 * fs1) + (I2 + g2) * fs2) * S : kOut;
+    }
 
     // plane strides are below 2^31 (checked by the launcher): 32 x 32 -> 64 products
     const unsigned as0 = (unsigned)a.av.s[0], cs0 = (unsigned)a.cv.s[0], ws0 = (unsigned)a.wv.s[0],
@@ -234,14 +356,14 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     auto mul64 = [](int i, unsigned st) { return (int64_t)((uint64_t)(unsigned)i * st); };
     // all loads are unconditional: a load under a branch makes the compiler
     // wait for every outstanding load where the paths join
-    auto load_plane = [&](int f, T (&v)[NRW], T (&vz)[NRW]) {
-        const int64_t po = mul64(f, as0) + (int64_t)RB * as1;
-        const __amdgpu_buffer_rsrc_t rA = make_rsrc(a.A + po, spanA);
-        const __amdgpu_buffer_rsrc_t rZ = make_rsrc(kZ ? a.Z + po : a.A, spanA);
+    using Cols = T[CPL];
+    auto load_plane = [&](int f, Cols (&v)[NRW], Cols (&vz)[NRW]) {
+        const int64_t po = mul64(f, as0);
 #pragma unroll
         for (int k = 0; k < NRW; k++) {
-            v[k] = buf_load<T>(rA, vA[k]);
-            if (kZ) vz[k] = buf_load<T>(rZ, vA[k]);
+            const int64_t o = po + (int64_t)gr[k] * as1;
+            buf_load_cols<kU>(make_rsrc(a.A + o, rin[k] ? rowA : 0u), cA, stepA, v[k]);
+            if (kZ) buf_load_cols<kU>(make_rsrc(a.Z + o, rin[k] ? rowA : 0u), cA, stepA, vz[k]);
         }
     };
 
@@ -254,47 +376,78 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
         constexpr int rgmax = RP ? ((RW - 1) % 2 ? RW - 1 : RW - 2) : ((RW - 1) % 2 ? RW - 2 : RW - 1);
         return (rgmax + RW * k < NR) || (rg + RW * k < NR);
     };
+    auto sC_at = [&](int k, int j) -> T& {
+        const int cj = cb + j;
+        return sCrow[RW * k * H + (cj & 1) * OB + (cj >> 1)];
+    };
     // Coefficients of plane f into sC (and C, W); returns through P the 2-D
     // interpolant of an even plane.  Ends with a barrier after the sC writes.
-    auto coef_plane = [&](int f, bool even, const T (&cur)[NRW], T (&P)[NRW], const T (&Pa)[NRW],
-                          const T (&Pb)[NRW]) {
+    auto coef_plane = [&](int f, bool even, const Cols (&cur)[NRW], Cols (&P)[NRW], const Cols (&Pa)[NRW],
+                          const Cols (&Pb)[NRW]) {
         if (!kDec) {
 #pragma unroll
             for (int k = 0; k < NRW; k++) {
                 if (!row_exists(k)) continue;
-                // coarse positions hold other classes: read them as zero
-                sCw[RW * k * H] = (even && !RP && ceven) ? T(0) : cur[k];
+#pragma unroll
+                for (int j = 0; j < CPL; j++) {
+                    // coarse positions hold other classes: read them as zero
+                    const bool ce = !((cb + j) & 1);
+                    sC_at(k, j) = (even && !RP && ce) ? T(0) : cur[k][j];
+                }
             }
             lds_barrier();
             return;
         }
         const bool fown = f >= oF0 && f < oF1;
-        const __amdgpu_buffer_rsrc_t rC = make_rsrc(a.C + mul64(f, cs0) + (int64_t)RB * cs1, fown ? spanC : 0u);
+        const int64_t pc = mul64(f, cs0);
+        auto rC = [&](int k) { return make_rsrc(a.C + pc + (int64_t)gr[k] * cs1, rowC); };
+        Cols cv[NRW];
         if (even) {
-            const __amdgpu_buffer_rsrc_t rW =
-                make_rsrc(a.W + mul64(f >> 1, ws0) + (int64_t)(RB >> 1) * ws1, fown ? spanW : 0u);
+            const int64_t pw = mul64(f >> 1, ws0);
+            auto rW = [&](int k) { return make_rsrc(a.W + pw + (int64_t)(gr[k] >> 1) * ws1, rowW); };
 #pragma unroll
-            for (int k = 0; k < NRW; k++)
-                if (row_exists(k)) sUw[RW * k * NCW] = cur[k];
+            for (int k = 0; k < NRW; k++) {
+                if (!row_exists(k)) continue;
+                if constexpr (CPL == 2) {
+                    typedef T T2 __attribute__((ext_vector_type(2)));
+                    T2 w2;
+                    w2.x = cur[k][0];
+                    w2.y = cur[k][1];
+                    *reinterpret_cast<T2*>(sUw + RW * k * NCW) = w2;
+                } else {
+                    sUw[RW * k * NCW] = cur[k][0];
+                }
+            }
             lds_barrier();
 #pragma unroll
             for (int k = 0; k < NRW; k++) {
                 if (!row_exists(k)) continue;
-                T p;
-                if (RP) {
-                    const T lo = lerp2(wcl, sUl[(RW * k - 1) * NCW], wch, sUr[(RW * k - 1) * NCW]);
-                    const T hi = lerp2(wcl, sUl[(RW * k + 1) * NCW], wch, sUr[(RW * k + 1) * NCW]);
-                    p = lerp2(wrl[k], lo, wrh[k], hi);
-                } else {
-                    p = wrl[k] * lerp2(wcl, sUl[RW * k * NCW], wch, sUr[RW * k * NCW]);
+                const T* const ru = sUrow + RW * k * NCW;
+#pragma unroll
+                for (int j = 0; j < CPL; j++) {
+                    const bool ce = !((cb + j) & 1);
+                    T p;
+                    if (CPL == 2 && j == 0) {
+                        // even column: the column weights are (1, 0)
+                        p = RP ? lerp2(wrl[k], ru[ul[0] - NCW], wrh[k], ru[ul[0] + NCW]) : wrl[k] * cur[k][0];
+                    } else if (RP) {
+                        const T lo = lerp2(wcl[j], ru[ul[j] - NCW], wch[j], ru[ur[j] - NCW]);
+                        const T hi = lerp2(wcl[j], ru[ul[j] + NCW], wch[j], ru[ur[j] + NCW]);
+                        p = lerp2(wrl[k], lo, wrh[k], hi);
+                    } else {
+                        p = wrl[k] * lerp2(wcl[j], ru[ul[j]], wch[j], ru[ur[j]]);
+                    }
+                    P[k][j] = p;
+                    const T c = cur[k][j] - p;  // 0 at coarse and outside nodes
+                    sC_at(k, j) = c;
+                    // coarse positions take u: the output of the finest step
+                    // needs it, deeper steps' values there are overwritten later
+                    cv[k][j] = (!RP && ce) ? cur[k][j] : c;
                 }
-                P[k] = p;
-                const T cv = cur[k] - p;  // 0 at coarse and outside nodes
-                sCw[RW * k * H] = cv;
-                // coarse positions take u: the output of the finest step
-                // needs it, deeper steps' values there are overwritten later
-                buf_store((!RP && ceven) ? cur[k] : cv, rC, vC[k]);
-                if (!RP) buf_store(cur[k], rW, vW[k]);
+                if (fown && rown[k]) {
+                    buf_store_cols<kU>(cv[k], rC(k), cC, stepC);
+                    if (!RP) buf_store(cur[k][jw], rW(k), cW);
+                }
             }
         } else {
             // odd plane: every node is fine; interpolate along dim 0 between
@@ -303,18 +456,21 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
 #pragma unroll
             for (int k = 0; k < NRW; k++) {
                 if (!row_exists(k)) continue;
-                const T cv = cur[k] - lerp2(wl, Pa[k], wh, Pb[k]);
-                sCw[RW * k * H] = cv;
-                buf_store(cv, rC, vC[k]);
+#pragma unroll
+                for (int j = 0; j < CPL; j++) {
+                    cv[k][j] = cur[k][j] - lerp2(wl, Pa[k][j], wh, Pb[k][j]);
+                    sC_at(k, j) = cv[k][j];
+                }
+                if (fown && rown[k]) buf_store_cols<kU>(cv[k], rC(k), cC, stepC);
             }
         }
         lds_barrier();
     };
 
-    // dim-2 then dim-1 stencils of the plane in sC: this thread's value of
+    // dim-2 then dim-1 stencils of the plane in sC: this thread's values of
     // the plane's contribution (zeros stand in for coarse and outside nodes,
     // so there are no masks or bounds)
-    auto reduce_plane = [&]() -> T {
+    auto reduce_plane = [&](T (&g)[NOUT]) {
 #pragma unroll
         for (int ps = 0; ps < NGP; ps++) {
             const int r = g1 + ps * (kThreads / GW);
@@ -322,86 +478,143 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
             const T* E = sC + r * H + g2;
             const T* O = sC + OB + r * H + g2;
             if (g2 < kT2)
-                sG[r * GW + g2] = k2[0] * E[0] + k2[1] * O[0] + k2[2] * E[1] + k2[3] * O[1] + k2[4] * E[2];
+                sG[r * GW + g2] = dot5(k2[0], E[0], k2[1], O[0], k2[2], E[1], k2[3], O[1], k2[4], E[2]);
         }
         lds_barrier();
-        if (kAct1) {
-            const T* Gp = sG + 2 * g1 * GW + g2;
-            return k1[0] * Gp[0] + k1[1] * Gp[GW] + k1[2] * Gp[2 * GW] + k1[3] * Gp[3 * GW] +
-                   k1[4] * Gp[4 * GW];
+#pragma unroll
+        for (int q = 0; q < NOUT; q++) {
+            if (kAct1) {
+                const T* Gp = sG + 2 * (g1 + q * (kThreads / GW)) * GW + g2;
+                g[q] = dot5(k1[q][0], Gp[0], k1[q][1], Gp[GW], k1[q][2], Gp[2 * GW], k1[q][3], Gp[3 * GW],
+                            k1[q][4], Gp[4 * GW]);
+            } else {
+                g[q] = sG[g2];
+            }
         }
-        return sG[g2];
     };
     // The next plane writes sU and sC only before its first barrier and sG
     // only after it; every reader of sC passed the dim-2 barrier and every
     // reader of sG reaches the next plane's first barrier only after reading.
-    auto store_f = [&](int i, T v) { buf_store(v, make_rsrc(a.F + mul64(i, fs0), spanF), vF); };
-
-    T X[NRW], XZ[NRW], Y[NRW], YZ[NRW], cur[NRW], Pp[NRW], Pn[NRW];
+    auto store_f = [&](int i, const T (&v)[NOUT], bool keep) {
 #pragma unroll
-    for (int k = 0; k < NRW; k++) {
-        X[k] = XZ[k] = Y[k] = YZ[k] = Pp[k] = Pn[k] = T(0);
-    }
+        for (int q = 0; q < NOUT; q++) {
+            if constexpr (kRowUni) {
+                const int i1 = I1 + g1 + q * (kThreads / GW);
+                buf_store(v[q], make_rsrc(a.F + mul64(i, fs0) + (int64_t)i1 * fs1, keep ? rowF : 0u), vF[q]);
+            } else {
+                buf_store(v[q], make_rsrc(a.F + mul64(i, fs0), keep ? spanF : 0u), vF[q]);
+            }
+        }
+    };
+
+    // plane buffers: a ring of D, so that D - 1 planes are in flight while
+    // one is consumed
+    constexpr int D = stream_ring<T, kDec, kZ>();
+    Cols B0[NRW], B1[NRW], B2[NRW], B3[NRW];  // B2, B3 unused (and dropped) when D = 2
+    Cols Z0[NRW], Z1[NRW];                    // unused (and dropped) without the correction
+    Cols cur[NRW], Pp[NRW], Pn[NRW];
+#pragma unroll
+    for (int k = 0; k < NRW; k++)
+#pragma unroll
+        for (int j = 0; j < CPL; j++) Pp[k][j] = Pn[k][j] = T(0);
     lds_barrier();  // tables
+    T g[NOUT];
 
     if (!kAct0) {
-        load_plane(0, X, XZ);
+        load_plane(0, B0, Z0);
 #pragma unroll
-        for (int k = 0; k < NRW; k++) cur[k] = kZ ? X[k] + XZ[k] : X[k];
+        for (int k = 0; k < NRW; k++)
+#pragma unroll
+            for (int j = 0; j < CPL; j++) cur[k][j] = kZ ? B0[k][j] + Z0[k][j] : B0[k][j];
         coef_plane(0, true, cur, Pn, Pp, Pp);
-        store_f(0, reduce_plane());
+        reduce_plane(g);
+        store_f(0, g, true);
         return;
     }
 
-    // Planes in the order F0, then pairs (F0+2k+2, F0+2k+1): an odd plane
-    // follows both even neighbours.  Two planes are in flight: X holds the
-    // odd planes, Y the even ones (planes past F1 re-read F1).  Each buffer
-    // is reloaded right after its last use, so no loaded register is copied
-    // (a copy would wait for the load).
+    // Planes in the order s_0 = F0, then pairs s_{2k+1} = F0+2k+2 (even),
+    // s_{2k+2} = F0+2k+1 (odd): an odd plane follows both even neighbours.
+    // Plane s_j sits in buffer j mod D and is replaced by s_{j+D} right
+    // after its last use, so no loaded register is ever copied (a copy would
+    // wait for the load); planes past F1 re-read F1.
+    auto seq = [&](int j) { return min(j == 0 ? F0 : ((j & 1) ? F0 + j + 1 : F0 + j - 1), F1); };
     const int K = (F1 - F0) / 2;
-    load_plane(F0, X, XZ);
-    load_plane(min(F0 + 2, F1), Y, YZ);
+    load_plane(seq(0), B0, Z0);
+    load_plane(seq(1), B1, Z1);
+    if constexpr (D > 2) {
+        load_plane(seq(2), B2, Z0);
+        load_plane(seq(3), B3, Z0);
+    }
     // running dim-0 sums of coarse planes A = F0/2 + k, B = A + 1, Cc = A + 2
-    T accA = T(0), accB = T(0), accC = T(0);
+    T accA[NOUT], accB[NOUT], accC[NOUT];
+#pragma unroll
+    for (int q = 0; q < NOUT; q++) accA[q] = accB[q] = accC[q] = T(0);
     const T* const k0 = sK0 + 5 * (F0 / 2 - P0 + 1) + 2;  // k0[5 (i - F0/2) + t]
-    auto consume = [&](int f, bool even, T (&B)[NRW], T (&BZ)[NRW], int fnext) {
+    auto consume = [&](int j, Cols (&B)[NRW], Cols (&BZ)[NRW]) {
+        const int f = seq(j);
+        const bool even = (j & 1) || j == 0;
         if (kZ) {
 #pragma unroll
-            for (int q = 0; q < NRW; q++) cur[q] = B[q] + BZ[q];
-            load_plane(fnext, B, BZ);
+            for (int q = 0; q < NRW; q++)
+#pragma unroll
+                for (int jj = 0; jj < CPL; jj++) cur[q][jj] = B[q][jj] + BZ[q][jj];
+            load_plane(seq(j + D), B, BZ);
             coef_plane(f, even, cur, Pn, Pp, Pn);
         } else {
             coef_plane(f, even, B, Pn, Pp, Pn);
-            load_plane(fnext, B, BZ);
+            load_plane(seq(j + D), B, BZ);
         }
     };
-    consume(F0, true, X, XZ, min(F0 + 1, F1));
-    {
-        const T g = reduce_plane();
-        accA += k0[0] * g;
-        accB += k0[5 - 2] * g;
+    consume(0, B0, Z0);
+    reduce_plane(g);
+#pragma unroll
+    for (int q = 0; q < NOUT; q++) {
+        accA[q] = fma(k0[0], g[q], accA[q]);
+        accB[q] = fma(k0[5 - 2], g[q], accB[q]);
     }
-    for (int k = 0; k < K; k++) {
+    // step k: even plane F0+2k+2 from buffer E, odd plane F0+2k+1 from O
+    auto step = [&](int k, Cols (&E)[NRW], Cols (&EZ)[NRW], Cols (&O)[NRW], Cols (&OZ)[NRW]) {
         const T* const kk = k0 + 5 * k;  // coarse plane ia = F0/2 + k completes in this step
 #pragma unroll
-        for (int q = 0; q < NRW; q++) Pp[q] = Pn[q];
-        consume(F0 + 2 * k + 2, true, Y, YZ, min(F0 + 2 * k + 4, F1));
-        T g = reduce_plane();
-        accA += kk[2] * g;
-        accB += kk[5] * g;
-        accC += kk[10 - 2] * g;
-        consume(F0 + 2 * k + 1, false, X, XZ, min(F0 + 2 * k + 3, F1));
-        g = reduce_plane();
-        accA += kk[1] * g;
-        accB += kk[5 - 1] * g;
+        for (int q = 0; q < NRW; q++)
+#pragma unroll
+            for (int j = 0; j < CPL; j++) Pp[q][j] = Pn[q][j];
+        consume(2 * k + 1, E, EZ);
+        reduce_plane(g);
+#pragma unroll
+        for (int q = 0; q < NOUT; q++) {
+            accA[q] = fma(kk[2], g[q], accA[q]);
+            accB[q] = fma(kk[5], g[q], accB[q]);
+            accC[q] = fma(kk[10 - 2], g[q], accC[q]);
+        }
+        consume(2 * k + 2, O, OZ);
+        reduce_plane(g);
+#pragma unroll
+        for (int q = 0; q < NOUT; q++) {
+            accA[q] = fma(kk[1], g[q], accA[q]);
+            accB[q] = fma(kk[5 - 1], g[q], accB[q]);
+        }
         const int ia = F0 / 2 + k;
-        if (ia >= P0) store_f(ia, accA);
-        accA = accB;
-        accB = accC;
-        accC = T(0);
+        store_f(ia, accA, ia >= P0);
+#pragma unroll
+        for (int q = 0; q < NOUT; q++) {
+            accA[q] = accB[q];
+            accB[q] = accC[q];
+            accC[q] = T(0);
+        }
+    };
+    if constexpr (D > 2) {
+        int k = 0;
+        for (; k + 1 < K; k += 2) {
+            step(k, B1, Z1, B2, Z0);
+            step(k + 1, B3, Z1, B0, Z0);
+        }
+        if (k < K) step(k, B1, Z1, B2, Z0);
+    } else {
+        for (int k = 0; k < K; k++) step(k, B1, Z1, B0, Z0);
     }
     // last coarse plane of the grid: its stencil has no right half
-    if (F1 == m0 - 1 && F1 / 2 < P1) store_f(F1 / 2, accA);
+    store_f(F1 / 2, accA, F1 == m0 - 1 && F1 / 2 < P1);
     };
     if (kAct1 && (rg & 1))
         run(std::true_type{});
