@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgr.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("mgr_api.cpp", "mgr_kernels.hip", "mgr_stream.hip", "mgr_solve.hip", "mgr_tail.hip",
+           ("mgr_api.cpp", "mgr_kernels.hip", "mgr_stream.hip", "mgr_recon.hip", "mgr_solve.hip", "mgr_tail.hip",
             "mgr_batch.hip", "mgr_adjoint.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -331,16 +331,7 @@ hipError_t launch_adj_cfg(AdjArgs<T> a, hipStream_t st)
     int chunk = c0;
     if (kAct0) {
         static int occ = 0;
-        if (occ == 0) {
-            int n = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kThreads, 0) != hipSuccess || n <= 0) n = 2;
-            occ = n;
-        }
-        int cus = 0, dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        const int nch = std::max(1, occ * cus / tiles);
+        const int nch = std::max(1, resident_per_cu(kern, occ) * device_cu_count() / tiles);
         chunk = (c0 + nch - 1) / nch;
         chunk = std::min(std::max(chunk, 1), kMaxChunk);
     }

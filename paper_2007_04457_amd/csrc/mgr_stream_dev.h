@@ -41,6 +41,18 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
     return (x < rem) ? x * (lo + 1) + local : rem * (lo + 1) + (x - rem) * lo + local;
 }
 
+// Workgroups of `kern` that one compute unit holds at once (cached per kernel).
+template <typename K>
+int resident_per_cu(K kern, int& cache)
+{
+    if (cache == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kThreads, 0) != hipSuccess || n <= 0) n = 2;
+        cache = n;
+    }
+    return cache;
+}
+
 // Geometry of the streaming level kernel, per problem dimensionality and
 // element size.  A lane owns CPL = 8 / sizeof(T) consecutive staged columns
 // (a column pair in FP32, one column in FP64), so that every global access of
