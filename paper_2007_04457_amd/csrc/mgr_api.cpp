@@ -614,6 +614,22 @@ int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st)
 {
     T* ws = (T*)p.ws;
     View3 fv = packed(p.lv[(size_t)k].mc);
+    {
+        // small coarse grids: every dimension in one launch when it fits
+        int dims[3], nd = 0;
+        SolveTables<T> tbs[3];
+        for (int s = 0; s < 3; s++) {
+            const int d = reverse ? s : 2 - s;
+            if (!p.active[d]) continue;
+            dims[nd] = d;
+            tbs[nd++] = solve_tables_of<T>(p, k, d);
+        }
+        if (solve_small_fits<T>(fv, dims, nd, tbs)) {
+            MGR_TRY(timed(KC_SOLVE, k, st, [&] { return launch_solve_small<T>(F, fv, dims, nd, tbs, st); }),
+                    "small solve launch");
+            return MGR_OK;
+        }
+    }
     for (int s = 0; s < 3; s++) {
         int d = reverse ? s : 2 - s;
         if (!p.active[d]) continue;

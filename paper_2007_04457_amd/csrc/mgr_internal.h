@@ -84,6 +84,15 @@ struct SolveTables {
 // In-place correction solve of F along dimension d.
 template <typename T>
 hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st);
+// All active dimensions of a small coarse grid in one workgroup (order:
+// dimensions dims[0], dims[1], ... of the nd listed), each fibre by the same
+// segment arithmetic as launch_solve_partitioned; returns hipErrorNotSupported
+// (launching nothing) unless every listed dimension is one segment long and
+// the grid fits in the workgroup's LDS.
+template <typename T>
+hipError_t launch_solve_small(T* F, View3 fv, const int* dims, int nd, const SolveTables<T>* tb, hipStream_t st);
+template <typename T>
+bool solve_small_fits(View3 fv, const int* dims, int nd, const SolveTables<T>* tb);
 
 // Single-workgroup kernel for the small coarse levels (mgr_tail.hip): all
 // level steps k0 .. k0 + nlev - 1 in one launch, in LDS.  A level step may

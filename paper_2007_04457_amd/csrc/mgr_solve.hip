@@ -77,6 +77,76 @@ __global__ void __launch_bounds__(kBlk) k_seg_final(T* __restrict__ F, FibreMap 
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlk - 1) / kBlk); }
 
+// ---- small coarse grids: every dimension in one workgroup -----------------
+// Once the coarse grid is a few ten thousand nodes, each of the per-dimension
+// launches above is bound by its own latency (load, a short serial sweep,
+// store).  This kernel keeps the grid in LDS and runs the dimensions one after
+// the other, one fibre per lane, with each fibre solved by seg_solve exactly
+// as above (one segment: no separators, and the separator terms the other
+// kernels add are zero), so it yields the values of the per-dimension
+// launches.
+constexpr int kSmallThreads = 1024;
+
+template <typename T>
+struct SmallSolveArgs {
+    T* F;
+    int n[3];
+    int nd, dims[3];
+    const T* L[3];
+    const T* U[3];
+    const T* IP[3];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char small_lds[];
+    T* const tab = reinterpret_cast<T*>(small_lds);  // [dim slot][L, U, IP][kSlot]
+    T* const g = tab + 9 * kSlot;
+    const int tid = threadIdx.x;
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int V = n0 * n1 * n2;
+    for (int e = tid; e < a.nd * 3 * kSlot; e += kSmallThreads) {
+        const int dd = e / (3 * kSlot), w = (e / kSlot) % 3, q = e % kSlot;
+        const T* src = (w == 0) ? a.L[dd] : (w == 1) ? a.U[dd] : a.IP[dd];
+        tab[e] = src[q];
+    }
+    // the grid in batches of 12 loads per lane, all in flight together
+    // (indices clamped into the grid: the loads are unconditional)
+    for (int b0 = 0; b0 < V; b0 += 12 * kSmallThreads) {
+        T tmp[12];
+#pragma unroll
+        for (int q = 0; q < 12; q++) tmp[q] = a.F[min(b0 + q * kSmallThreads + tid, V - 1)];
+#pragma unroll
+        for (int q = 0; q < 12; q++)
+            if (b0 + q * kSmallThreads + tid < V) g[b0 + q * kSmallThreads + tid] = tmp[q];
+    }
+    __syncthreads();
+    const int cs[3] = {n1 * n2, n2, 1};
+    for (int dd = 0; dd < a.nd; dd++) {
+        const int d = a.dims[dd];
+        const int n = a.n[d], sd = cs[d];
+        // fibres along d, indexed by the other two coordinates (inner first)
+        const int da = (d == 0) ? 1 : 0, db = (d == 2) ? 1 : 2;
+        const int nb = a.n[db], nfib = a.n[da] * nb;
+        const T* L = tab + (3 * dd + 0) * kSlot;
+        const T* U = tab + (3 * dd + 1) * kSlot;
+        const T* IP = tab + (3 * dd + 2) * kSlot;
+        for (int f = tid; f < nfib; f += kSmallThreads) {
+            T* p = g + (f / nb) * cs[da] + (f % nb) * cs[db];
+            T v[kSlot];
+#pragma unroll
+            for (int q = 0; q < kSlot; q++) v[q] = p[min(q, n - 1) * sd];
+            seg_solve(v, L, U, IP);
+#pragma unroll
+            for (int q = 0; q < kSlot; q++)
+                if (q < n) p[q * sd] = v[q];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < V; e += kSmallThreads) a.F[e] = g[e];
+}
+
 }  // namespace
 
 // Solve along dimension d of the packed array F (shape fv.n), in place.  Yb
@@ -116,6 +186,66 @@ hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T*
     return hipGetLastError();
 }
 
+// LDS the small-grid kernel may use on the current device (0: none).
+template <typename T>
+int small_solve_lds()
+{
+    static int max_lds[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (max_lds[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        max_lds[dev] = v;
+        if (v > 65536 &&
+            hipFuncSetAttribute((const void*)k_solve_small<T>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+                hipSuccess) {
+            (void)hipGetLastError();  // not sticky: keep it from the next launch check
+            max_lds[dev] = 65536;
+        }
+    }
+    return max_lds[dev];
+}
+
+template <typename T>
+size_t small_solve_bytes(View3 fv)
+{
+    return (9 * (size_t)kSlot + (size_t)(fv.n[0] * fv.n[1] * fv.n[2])) * sizeof(T);
+}
+
+template <typename T>
+bool solve_small_fits(View3 fv, const int* dims, int nd, const SolveTables<T>* tb)
+{
+    if (nd < 1 || nd > 3) return false;
+    for (int i = 0; i < nd; i++)
+        if (tb[i].S != 1 || fv.n[dims[i]] > kSlot) return false;
+    return small_solve_bytes<T>(fv) <= (size_t)small_solve_lds<T>();
+}
+
+template <typename T>
+hipError_t launch_solve_small(T* F, View3 fv, const int* dims, int nd, const SolveTables<T>* tb, hipStream_t st)
+{
+    if (!solve_small_fits(fv, dims, nd, tb)) return hipErrorNotSupported;
+    SmallSolveArgs<T> a;
+    a.F = F;
+    for (int d = 0; d < 3; d++) a.n[d] = (int)fv.n[d];
+    a.nd = nd;
+    for (int i = 0; i < nd; i++) {
+        a.dims[i] = dims[i];
+        a.L[i] = tb[i].L;
+        a.U[i] = tb[i].U;
+        a.IP[i] = tb[i].IP;
+    }
+    hipLaunchKernelGGL(k_solve_small<T>, dim3(1), dim3(kSmallThreads), small_solve_bytes<T>(fv), st, a);
+    return hipGetLastError();
+}
+
+template bool solve_small_fits<float>(View3, const int*, int, const SolveTables<float>*);
+template bool solve_small_fits<double>(View3, const int*, int, const SolveTables<double>*);
+template hipError_t launch_solve_small<float>(float*, View3, const int*, int, const SolveTables<float>*, hipStream_t);
+template hipError_t launch_solve_small<double>(double*, View3, const int*, int, const SolveTables<double>*,
+                                               hipStream_t);
 template hipError_t launch_solve_partitioned<float>(float*, View3, int, SolveTables<float>, float*,
                                                     hipStream_t);
 template hipError_t launch_solve_partitioned<double>(double*, View3, int, SolveTables<double>, double*,
