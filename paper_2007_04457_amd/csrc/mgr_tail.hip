@@ -21,6 +21,7 @@ namespace mgr {
 namespace {
 
 constexpr int kT = kTailThreads;
+constexpr int kTB = 6;  // grid loads in flight per lane
 
 struct TailShape {
     int m[3], mc[3];
@@ -60,30 +61,45 @@ struct LdsTab {
 template <typename T>
 __device__ LdsTab<T> stage_tables(const TailLevel<T>& L, T* stab)
 {
+    // Layout per active dimension: w (2 m), K (5 mc), lf, ip, up (mc each).
+    // All tables are copied in one pass over their concatenation, one
+    // element per lane and round, so a level costs one memory latency here
+    // rather than one per table.
     LdsTab<T> t;
-    int off = 0;
+    const T* src[15];  // segment 5 d + j (empty for inactive dimensions)
+    int len[15], off = 0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         const bool act = L.m[d] > 1;
-        const int m = L.m[d], mc = L.mc[d];
+        const int m = act ? L.m[d] : 0, mc = act ? L.mc[d] : 0;
         t.w[d] = stab + off;
-        if (act)
-            for (int e = threadIdx.x; e < 2 * m; e += kT) t.w[d][e] = L.tb.w[d][e];
-        off += act ? 2 * m : 0;
-        t.K[d] = stab + off;
-        if (act)
-            for (int e = threadIdx.x; e < 5 * mc; e += kT) t.K[d][e] = L.tb.K[d][e];
-        off += act ? 5 * mc : 0;
-        t.lf[d] = stab + off;
-        t.ip[d] = stab + off + (act ? mc : 0);
-        t.up[d] = stab + off + (act ? 2 * mc : 0);
-        if (act)
-            for (int e = threadIdx.x; e < mc; e += kT) {
-                t.lf[d][e] = L.lf[d][e];
-                t.ip[d][e] = L.ip[d][e];
-                t.up[d][e] = L.up[d][e];
-            }
-        off += act ? 3 * mc : 0;
+        t.K[d] = t.w[d] + 2 * m;
+        t.lf[d] = t.K[d] + 5 * mc;
+        t.ip[d] = t.lf[d] + mc;
+        t.up[d] = t.ip[d] + mc;
+        src[5 * d + 0] = L.tb.w[d];
+        len[5 * d + 0] = 2 * m;
+        src[5 * d + 1] = L.tb.K[d];
+        len[5 * d + 1] = 5 * mc;
+        src[5 * d + 2] = L.lf[d];
+        len[5 * d + 2] = mc;
+        src[5 * d + 3] = L.ip[d];
+        len[5 * d + 3] = mc;
+        src[5 * d + 4] = L.up[d];
+        len[5 * d + 4] = mc;
+        off += 2 * m + 8 * mc;
+    }
+    for (int e0 = 0; e0 < off; e0 += kT) {
+        const int e = e0 + threadIdx.x;
+        // the element's source, selected over the (unrolled) segment list
+        const T* ps = nullptr;
+        int base = 0;
+#pragma unroll
+        for (int sg = 0; sg < 15; sg++) {
+            if (e >= base && e < base + len[sg]) ps = src[sg] + (e - base);
+            base += len[sg];
+        }
+        if (e < off) stab[e] = *ps;
     }
     return t;
 }
@@ -230,11 +246,20 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, const T* src, T*
         {
             const TailLevel<T>& L = a.lv[0];
             const TailShape s = shape_of(L.m, L.mc);
-            for (int idx = threadIdx.x; idx < s.V; idx += kT) {
-                int j0, j1, j2;
-                dec3(idx, s.m, j0, j1, j2);
-                R.U[idx] = (a.k0 == 0) ? src[j0 * st[0] + j1 * st[1] + j2 * st[2]]
-                                       : L.Wk[idx] + (a.Z0 ? a.Z0[idx] : T(0));
+            // in batches of kTB loads per lane, all in flight together
+            for (int b0 = 0; b0 < s.V; b0 += kTB * kT) {
+                T tmp[kTB];
+#pragma unroll
+                for (int q = 0; q < kTB; q++) {
+                    const int idx = min(b0 + q * kT + (int)threadIdx.x, s.V - 1);
+                    int j0, j1, j2;
+                    dec3(idx, s.m, j0, j1, j2);
+                    tmp[q] = (a.k0 == 0) ? src[j0 * st[0] + j1 * st[1] + j2 * st[2]]
+                                         : L.Wk[idx] + (a.Z0 ? a.Z0[idx] : T(0));
+                }
+#pragma unroll
+                for (int q = 0; q < kTB; q++)
+                    if (b0 + q * kT + (int)threadIdx.x < s.V) R.U[b0 + q * kT + threadIdx.x] = tmp[q];
             }
         }
         for (int l = 0; l < a.nlev; l++) {
@@ -290,10 +315,18 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, const T* src, T*
             const TailShape s = shape_of(L.m, L.mc);
             const LdsTab<T> t = stage_tables(L, stab);
             const int64_t v0 = st[0] << k, v1 = st[1] << k, v2 = st[2] << k;
-            for (int idx = threadIdx.x; idx < s.V; idx += kT) {
-                int j0, j1, j2;
-                dec3(idx, s.m, j0, j1, j2);
-                R.U[idx] = (((j0 | j1 | j2) & 1) == 0) ? T(0) : src[j0 * v0 + j1 * v1 + j2 * v2];
+            for (int b0 = 0; b0 < s.V; b0 += kTB * kT) {
+                T tmp[kTB];
+#pragma unroll
+                for (int q = 0; q < kTB; q++) {
+                    const int idx = min(b0 + q * kT + (int)threadIdx.x, s.V - 1);
+                    int j0, j1, j2;
+                    dec3(idx, s.m, j0, j1, j2);
+                    tmp[q] = (((j0 | j1 | j2) & 1) == 0) ? T(0) : src[j0 * v0 + j1 * v1 + j2 * v2];
+                }
+#pragma unroll
+                for (int q = 0; q < kTB; q++)
+                    if (b0 + q * kT + (int)threadIdx.x < s.V) R.U[b0 + q * kT + threadIdx.x] = tmp[q];
             }
             __syncthreads();
             lds_load_vector(R.U, R.P1, R.P2, R.F, s, t);
