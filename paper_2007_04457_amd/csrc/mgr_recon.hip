@@ -426,13 +426,16 @@ hipError_t launch_recon_al(StreamArgs<T> a, hipStream_t st)
     return hipGetLastError();
 }
 
-// The line-aligned form takes 3-D grids whose output has unit column stride
-// and rows short enough that the last tile of a row owns at most 64
-// columns (m2 = 64 q + 1, or m2 <= 33), with offsets below 2^31 bytes.
+// The line-aligned form takes 3-D grids whose coefficients and output both
+// have unit column stride (the finest level step: on coarser steps the
+// coefficients are strided and the per-lane kernel measured faster) and rows
+// short enough that the last tile of a row owns at most 64 columns
+// (m2 = 64 q + 1, or m2 <= 33), with offsets below 2^31 bytes.
 template <typename T>
 bool recon_al_ok(const StreamArgs<T>& a)
 {
-    if (a.av.n[0] < 2 || a.av.n[1] < 2 || a.cv.s[2] != 1 || ((uintptr_t)a.C % sizeof(T)) != 0) return false;
+    if (a.av.n[0] < 2 || a.av.n[1] < 2 || a.av.s[2] != 1 || a.cv.s[2] != 1 || ((uintptr_t)a.C % sizeof(T)) != 0)
+        return false;
     const int64_t m2 = a.av.n[2];
     if (!((m2 - 1) % 64 == 0 || m2 <= 33)) return false;
     const int64_t span = std::max((a.av.n[1] - 1) * a.av.s[1] + (m2 - 1) * a.av.s[2] + 1,
