@@ -147,6 +147,17 @@ void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2);
 template <typename T>
 hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st);
 
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber so
+// each XCD works on a contiguous range of tiles: neighbouring tiles then share
+// its L2, for halo re-reads and for the cache lines their stores split.
+__device__ __forceinline__ int remap_xcd(int bid, int nb)
+{
+    const int nx = 8;
+    const int lo = nb / nx, rem = nb % nx;
+    const int x = bid % nx, local = bid / nx;
+    return (x < rem) ? x * (lo + 1) + local : rem * (lo + 1) + (x - rem) * lo + local;
+}
+
 // ---- batched decomposition (mgr_batch.hip) ----------------------------------
 // Work items: one workgroup's share of one stage of one level step of one
 // field.  Items are grouped into waves (level step k, stage s) over all

@@ -37,7 +37,10 @@ k_solve_strided_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb)
 {
     __shared__ StridedSmem<T> sm;
     const int s = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    solve_strided_tile<T, 64, true>(F, m, tb, (int64_t)blockIdx.x * 64, s, (int)threadIdx.x, 64 * m.S,
+    // neighbouring fibre groups split cache lines of every segment row they
+    // write: keep them on one XCD (one L2)
+    const int bx = remap_xcd((int)blockIdx.x, (int)gridDim.x);
+    solve_strided_tile<T, 64, true>(F, m, tb, (int64_t)bx * 64, s, (int)threadIdx.x, 64 * m.S,
                               (int)(threadIdx.y * 64 + threadIdx.x), sm);
 }
 

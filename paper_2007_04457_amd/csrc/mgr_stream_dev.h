@@ -30,17 +30,6 @@ __device__ __forceinline__ T dot5(T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3
     return fma(a4, b4, fma(a3, b3, fma(a2, b2, fma(a1, b1, a0 * b0))));
 }
 
-// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber so
-// each XCD works on a contiguous range of tiles and neighbouring tiles share
-// its L2 for the halo re-reads.
-__device__ __forceinline__ int remap_xcd(int bid, int nb)
-{
-    const int nx = 8;
-    const int lo = nb / nx, rem = nb % nx;
-    const int x = bid % nx, local = bid / nx;
-    return (x < rem) ? x * (lo + 1) + local : rem * (lo + 1) + (x - rem) * lo + local;
-}
-
 // Workgroups of `kern` that one compute unit holds at once (cached per kernel).
 template <typename K>
 int resident_per_cu(K kern, int& cache)
