@@ -80,6 +80,7 @@ __global__ void __launch_bounds__(kBlk) k_seg_final(T* __restrict__ F, FibreMap 
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kBlk - 1) / kBlk); }
 
+
 // ---- small coarse grids: every dimension in one workgroup -----------------
 // Once the coarse grid is a few ten thousand nodes, each of the per-dimension
 // launches above is bound by its own latency (load, a short serial sweep,

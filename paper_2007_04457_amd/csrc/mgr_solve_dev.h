@@ -156,29 +156,37 @@ struct RowsSmem {
     T septab[5][kLdsTab ? kMaxSegWG : kBlk];    // sub, sup, sl, sip, su at separators
 };
 
-// Rows row0 .. row0 + nrows - 1 (nrows * S <= kBlk, nrows * n <= kSpan).
-template <typename T, int kSpan, bool kLdsTab>
-__device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMap& m,
-                                                const SolveTables<T>& tb, int64_t row0, int nrows,
-                                                RowsSmem<T, kSpan, kLdsTab>& sm)
+// Rows row0 .. row0 + nrows - 1 (nrows * S <= kBlk, nrows * n <= kSpan),
+// in phases: the span's loads into registers (all in flight together,
+// indices clamped into the span so the loads are unconditional), their LDS
+// staging, the segment tables, the solve in LDS, and the span's stores.
+template <typename T, int kSpan>
+__device__ __forceinline__ void rows_load(const T* __restrict__ F, int64_t row0, int span, int n,
+                                          T (&tmp)[(kSpan + kBlk - 1) / kBlk])
 {
-    const int n = (int)m.n;
-    const int span = nrows * n;
-    T* g = F + row0 * n;
-    // every load of the span issued before the first LDS write, so that they
-    // are all in flight together (indices clamped into the span: the loads
-    // are unconditional)
-    {
-        constexpr int kLoads = (kSpan + kBlk - 1) / kBlk;
-        T tmp[kLoads];
+    // one descriptor over the span (past its end the loads read zero), one
+    // 32-bit offset per load
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(F + row0 * n, (unsigned)span * (unsigned)sizeof(T));
+    const unsigned o = threadIdx.x * (unsigned)sizeof(T);
 #pragma unroll
-        for (int q = 0; q < kLoads; q++) tmp[q] = g[min(q * kBlk + (int)threadIdx.x, span - 1)];
+    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) tmp[q] = buf_load<T>(r, o + (unsigned)(q * kBlk * sizeof(T)));
+}
+
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void rows_stage(const T (&tmp)[(kSpan + kBlk - 1) / kBlk], int span,
+                                           RowsSmem<T, kSpan, kLdsTab>& sm)
+{
 #pragma unroll
-        for (int q = 0; q < kLoads; q++) {
-            const int e = q * kBlk + (int)threadIdx.x;
-            if (e < span) sm.f[padded(e)] = tmp[q];
-        }
+    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) {
+        const int e = q * kBlk + (int)threadIdx.x;
+        if (e < span) sm.f[padded(e)] = tmp[q];
     }
+}
+
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void rows_tables(const FibreMap& m, const SolveTables<T>& tb,
+                                            RowsSmem<T, kSpan, kLdsTab>& sm)
+{
     if (kLdsTab)
         for (int e = threadIdx.x; e < m.S * kSlot; e += kBlk) {
             sm.tab[0][e] = tb.L[e];
@@ -187,8 +195,8 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
             sm.tab[3][e] = tb.A[e];
             sm.tab[4][e] = tb.B[e];
         }
-    // separator tables: the separator sweep below is serial, so each of its
-    // steps must find them in LDS rather than wait on a global load
+    // separator tables: the separator sweep is serial, so each of its steps
+    // must find them in LDS rather than wait on a global load
     for (int e = threadIdx.x; e < m.S; e += kBlk) {
         sm.septab[0][e] = tb.ssub[e];
         sm.septab[1][e] = tb.ssup[e];
@@ -196,6 +204,16 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
         sm.septab[3][e] = tb.sip[e];
         sm.septab[4][e] = tb.su[e];
     }
+}
+
+// The solve of the staged rows, in LDS.  Starts after a barrier that
+// follows the staging, ends with the solution in sm.f and a barrier.
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void rows_solve_lds(const FibreMap& m, const SolveTables<T>& tb, int nrows,
+                                               RowsSmem<T, kSpan, kLdsTab>& sm)
+{
+    auto bar = [] { __syncthreads(); };
+    const int n = (int)m.n;
     const int r = threadIdx.x / m.S, s = threadIdx.x % m.S;
     const bool active = r < nrows;
     const int rr = active ? r : 0;
@@ -207,14 +225,13 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
     const T* tI = kLdsTab ? &sm.tab[2][so] : tb.IP + so;
     const T* tA = kLdsTab ? &sm.tab[3][so] : tb.A + so;
     const T* tB = kLdsTab ? &sm.tab[4][so] : tb.B + so;
-    __syncthreads();
     T v[kSlot];
 #pragma unroll
     for (int q = 0; q < kSlot; q++) v[q] = sm.f[padded(rr * n + lo + min(q, len - 1))];
     const T ylast = seg_solve(v, tL, tU, tI);
     sm.end[0][threadIdx.x] = v[0];
     sm.end[1][threadIdx.x] = ylast;
-    __syncthreads();
+    bar();
     if (active && s == 0 && m.S > 1) {
         // row r's separators live in sm.f at r*n + k*kSeg
         const int t0 = threadIdx.x;
@@ -232,17 +249,42 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
             sm.f[e] = z;
         }
     }
-    __syncthreads();
+    bar();
     const T zl = (s > 0) ? sm.f[padded(rr * n + s * kSeg)] : T(0);
     const T zr = (s < m.S - 1) ? sm.f[padded(rr * n + (s + 1) * kSeg)] : T(0);
-    __syncthreads();  // every lane has read its separators
+    bar();  // every lane has read its separators
     if (active) {
 #pragma unroll
         for (int q = 0; q < kSlot; q++)
             if (q < len) sm.f[padded(r * n + lo + q)] = v[q] + tA[q] * zl + tB[q] * zr;
     }
-    __syncthreads();
+    bar();
+}
+
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void rows_store(T* __restrict__ F, int64_t row0, int span, int n,
+                                           const RowsSmem<T, kSpan, kLdsTab>& sm)
+{
+    T* g = F + row0 * n;
     for (int e = threadIdx.x; e < span; e += kBlk) g[e] = sm.f[padded(e)];
+}
+
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMap& m,
+                                                const SolveTables<T>& tb, int64_t row0, int nrows,
+                                                RowsSmem<T, kSpan, kLdsTab>& sm)
+{
+    const int n = (int)m.n;
+    const int span = nrows * n;
+    {
+        T tmp[(kSpan + kBlk - 1) / kBlk];
+        rows_load<T, kSpan>(F, row0, span, n, tmp);
+        rows_stage<T, kSpan, kLdsTab>(tmp, span, sm);
+    }
+    rows_tables(m, tb, sm);
+    __syncthreads();
+    rows_solve_lds<T, kSpan, kLdsTab>(m, tb, nrows, sm);
+    rows_store(F, row0, span, n, sm);
 }
 
 // ---- long fibres: three launches through global memory ---------------------

@@ -12,16 +12,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Workgroup barrier that waits only for this wave's LDS traffic.  HIP's
-// __syncthreads() also drains outstanding global loads, which would stall the
-// register prefetch of the next plane at every barrier; nothing here needs
-// global memory ordered across the barrier (each output is written by one
-// thread and never read back inside the kernel).
-__device__ __forceinline__ void lds_barrier()
-{
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
 // Five-term dot product with a fixed association and rounding (an explicit
 // FMA chain), so that every kernel that inlines it rounds identically.
 template <typename T>
@@ -97,54 +87,7 @@ constexpr int stream_min_waves()
 {
     return stream_ring<T, kDec, kZ>() == 4 ? 5 : 1;
 }
-constexpr unsigned kOut = 0x80000000u;  // buffer offset past every range: loads 0, stores dropped
 
-// Marks a value the same in every lane (kept in scalar registers).
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double uni(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Raw buffer access (gfx9 descriptor): the hardware range check turns an
-// offset at or past `bytes` into a load of zero or a dropped store.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes)
-{
-    // base and size are wave-uniform; say so, or the compiler loops over lanes
-    const unsigned long long b = (unsigned long long)base;
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
-    void* ub = (void*)(((unsigned long long)hi << 32) | lo);
-    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, __builtin_amdgcn_readfirstlane((int)bytes), 0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
-template <>
-__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-template <>
-__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
-}
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
-}
 // A lane's CPL consecutive columns of one row.  FP32 pairs move as one
 // 8-byte access where the columns are adjacent in memory (kU), else as two
 // 4-byte accesses `step` bytes apart.  The hardware range check is per
