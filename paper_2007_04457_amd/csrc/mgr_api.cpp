@@ -63,7 +63,12 @@ struct Plan {
     void* ws = nullptr;
     size_t ws_bytes = 0, tables_bytes = 0, esize = 4;
     std::vector<size_t> Woff;  // W_k element offsets, k = 1..L (index k)
-    size_t P1 = 0, P2 = 0, F = 0, F2 = 0, Tb = 0, Yb = 0;  // F, F2: corrections of even, odd level steps
+    size_t F = 0, F2 = 0, Tb = 0, Yb = 0;  // F, F2: corrections of even, odd level steps
+    size_t Yb2 = 0;  // long-fibre solve scratch for the coarser level steps of a recomposition
+    // Recomposition computes every level's correction before it is applied,
+    // so it keeps one buffer per level step: Zrec[0] = F, Zrec[1] = F2, then
+    // regions of their own.
+    std::vector<size_t> Zrec;
 };
 
 std::mutex g_mu;
@@ -406,7 +411,8 @@ int build_plan(Plan& p, const double* const* coords)
             push_table(host, sv.su, &ly.su[d]);
         }
     }
-    // workspace: W_1..W_L, load-vector ping-pong P1/P2, F, adjoint buffer Tb
+    // workspace: W_1..W_L, corrections F, F2 (and per level for
+    // recomposition), adjoint buffer Tb, long-fibre solve scratch Yb
     const size_t al = 256 / sizeof(T);
     size_t off = 0;
     p.Woff.assign((size_t)L + 1, 0);
@@ -424,20 +430,26 @@ int build_plan(Plan& p, const double* const* coords)
         sh[d] = (sh[d] + 1) / 2;
         pass_sizes.push_back(sh[0] * sh[1] * sh[2]);
     }
-    size_t P1 = pass_sizes.size() >= 2 ? (size_t)pass_sizes[0] : 0;
-    size_t P2 = pass_sizes.size() >= 3 ? (size_t)pass_sizes[1] : 0;
     size_t Fn = L > 0 ? (size_t)pass_sizes.back() : 0;
-    p.P1 = off; off = align_up(off + P1, al);
-    p.P2 = off; off = align_up(off + P2, al);
     p.F = off;  off = align_up(off + Fn, al);
-    {
-        int64_t v1 = 1;
-        for (int d = 0; d < 3; d++) v1 *= p.active[d] ? ((p.n[d] - 1) >> 2) + 1 : 1;
-        p.F2 = off;
-        off = align_up(off + (L > 1 ? (size_t)v1 : 0), al);
+    int64_t v1 = 1;  // coarse grid of level step 1 (= level grid 2)
+    for (int d = 0; d < 3; d++) v1 *= p.active[d] ? ((p.n[d] - 1) >> 2) + 1 : 1;
+    p.F2 = off;
+    off = align_up(off + (L > 1 ? (size_t)v1 : 0), al);
+    p.Zrec.assign((size_t)L, 0);
+    for (int k = 0; k < L; k++) {
+        if (k < 2) {
+            p.Zrec[(size_t)k] = (k == 0) ? p.F : p.F2;
+            continue;
+        }
+        int64_t v = 1;  // coarse grid of level step k = level grid k + 1
+        for (int d = 0; d < 3; d++) v *= p.active[d] ? ((p.n[d] - 1) >> (k + 1)) + 1 : 1;
+        p.Zrec[(size_t)k] = off;
+        off = align_up(off + (size_t)v, al);
     }
     p.Tb = off; off = align_up(off + (L > 0 ? (size_t)V0 : 0), al);
     p.Yb = off; off = align_up(off + 2 * Fn / kSeg + 64, al);
+    p.Yb2 = off; off = align_up(off + (L > 1 ? 2 * (size_t)v1 / kSeg + 64 : 0), al);
     p.esize = sizeof(T);
     p.ws_bytes = off * sizeof(T);
     p.tables_bytes = host.size() * sizeof(T);
@@ -586,7 +598,7 @@ T* corr(const Plan& p, int k, void* ws = nullptr)
 // vector goes to corr(k).
 template <typename T>
 int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 av, T* C, View3 cv,
-                 T* W, bool write_coarse, hipStream_t st)
+                 T* W, bool write_coarse, hipStream_t st, T* Fout = nullptr)
 {
     const LevelLayout& ly = p.lv[(size_t)k];
     StreamArgs<T> a;
@@ -597,7 +609,7 @@ int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 a
     a.cv = cv;
     a.W = W;
     a.wv = packed(ly.mc);
-    a.F = corr<T>(p, k);
+    a.F = Fout ? Fout : corr<T>(p, k);
     a.fv = packed(ly.mc);
     a.tb = tables_of<T>(p, k);
     a.write_coarse = write_coarse ? 1 : 0;
@@ -610,7 +622,7 @@ int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 a
 
 // Correction solves of level step k on F along every dimension, in place.
 template <typename T>
-int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st)
+int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = nullptr)
 {
     T* ws = (T*)p.ws;
     View3 fv = packed(p.lv[(size_t)k].mc);
@@ -635,7 +647,7 @@ int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st)
         if (!p.active[d]) continue;
         SolveTables<T> tb = solve_tables_of<T>(p, k, d);
         MGR_TRY(timed(KC_SOLVE, k, st,
-                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, ws + p.Yb, st); }),
+                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, Yb ? Yb : ws + p.Yb, st); }),
                 "solve launch");
     }
     return MGR_OK;
@@ -773,6 +785,48 @@ int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     return MGR_OK;
 }
 
+// Two more streams per device for the recomposition's corrections (default
+// priority): one for the finest level step, one for the coarser ones, with
+// one event per level step; the enqueueing is serialised.
+constexpr int kMaxLevels = 64;  // above any level count of an int64 extent
+struct AuxStream {
+    hipStream_t s = nullptr, s0 = nullptr;
+    hipEvent_t start = nullptr;
+    hipEvent_t done[kMaxLevels] = {};
+};
+std::mutex g_aux_mu;
+AuxStream g_aux[64];
+
+hipError_t aux_stream(AuxStream** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    AuxStream& a = g_aux[dev];
+    if (!a.s) {
+        e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipStreamCreateWithFlags(&a.s0, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&a.start, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < kMaxLevels; k++) {
+            e = hipEventCreateWithFlags(&a.done[k], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+    }
+    *out = &a;
+    return hipSuccess;
+}
+
+// Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
+// The correction z_k of every level step depends on the stored coefficients
+// alone (its load vector is formed from them), so they are computed on two
+// more streams (the finest level step on one, the coarser ones, coarsest
+// first, on the other) while the caller's stream runs the coarsest levels
+// and the interpolations, each waiting only for its own z_k: the
+// latency-bound small levels overlap the bandwidth-bound finest ones.
 template <typename T>
 int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
@@ -782,6 +836,25 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     T* dst = (T*)dst_;
     T* ws = (T*)p.ws;
     const int kt = tail_start(p);
+    std::unique_lock<std::mutex> lk(g_aux_mu);
+    AuxStream* aux = nullptr;
+    if (kt > 0) {
+        MGR_TRY(aux_stream(&aux), "auxiliary stream");
+        MGR_TRY(hipEventRecord(aux->start, st), "fork event");
+        MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
+        if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
+        for (int i = 0; i < kt; i++) {
+            const int k = (i == 0) ? 0 : kt - i;  // finest first (own stream), then coarsest first
+            hipStream_t sk = (k == 0) ? aux->s0 : aux->s;
+            View3 cv = level_view(p, k);
+            T* z = ws + p.Zrec[(size_t)k];
+            int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z);
+            if (rc) return rc;
+            rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2);
+            if (rc) return rc;
+            MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
+        }
+    }
     if (kt < L) {
         TailArgs<T> a = tail_args<T>(p, kt, src, dst);
         a.Z0 = nullptr;
@@ -795,13 +868,10 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
         View3 cv = level_view(p, k);
-        int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, st);
-        if (rc) return rc;
-        rc = solve_all<T>(p, k, false, corr<T>(p, k), st);
-        if (rc) return rc;
+        MGR_TRY(hipStreamWaitEvent(st, aux->done[k], 0), "level wait");
         StreamArgs<T> a;
         a.A = src;
-        a.Z = corr<T>(p, k);
+        a.Z = ws + p.Zrec[(size_t)k];
         a.av = cv;
         a.C = (k == 0) ? dst : ws + p.Woff[(size_t)k];
         a.cv = (k == 0) ? full_view(p) : packed(ly.m);
