@@ -75,7 +75,15 @@ int mgr_decompose(const void* src, void* dst, int dtype, int ndim,
                   int nlevels, void* stream);
 
 /* Recomposition: the exact inverse of mgr_decompose, coarsest level first
- * (Sec. II-A, overall process). Reads a refactored array from src. */
+ * (Sec. II-A, overall process). Reads a refactored array from src.
+ * The corrections of the level steps (load vector of the stored
+ * coefficients and the solves) run on two library-owned streams of the
+ * current device, forked from `stream` and joined back into it with events,
+ * so the call may be captured into a graph like any other (prepare the
+ * problem first with mgr_prepare, which also creates those streams).
+ * Recompositions enqueued on different streams share the two streams: their
+ * corrections run in enqueue order, and a recomposition must not be
+ * enqueued from another thread while a recomposition is being captured. */
 int mgr_recompose(const void* src, void* dst, int dtype, int ndim,
                   const int64_t* shape, const double* const* coords,
                   int nlevels, void* stream);
@@ -90,8 +98,10 @@ int mgr_decompose_adjoint(const void* src, void* dst, int dtype, int ndim,
                           int nlevels, void* stream);
 
 /* Builds and uploads the tables and allocates the workspace of a problem
- * (synchronously), so that later calls on a capturing stream allocate
- * nothing.  Optional: the compute entry points prepare on first use. */
+ * (synchronously), and creates the recomposition's streams of the current
+ * device, so that later calls on a capturing stream allocate and create
+ * nothing.  Optional: the compute entry points prepare on first use, except
+ * on a capturing stream (MGR_ERR_CAPTURE). */
 int mgr_prepare(int dtype, int ndim, const int64_t* shape,
                 const double* const* coords, int nlevels);
 

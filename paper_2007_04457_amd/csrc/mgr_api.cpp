@@ -820,6 +820,14 @@ hipError_t aux_stream(AuxStream** out)
     return hipSuccess;
 }
 
+// Whether the current device's auxiliary streams exist (caller holds g_aux_mu).
+bool aux_ready()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    return g_aux[dev].s != nullptr;
+}
+
 // Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
 // The correction z_k of every level step depends on the stored coefficients
 // alone (its load vector is formed from them), so they are computed on two
@@ -839,6 +847,8 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     std::unique_lock<std::mutex> lk(g_aux_mu);
     AuxStream* aux = nullptr;
     if (kt > 0) {
+        if (!aux_ready() && capturing(st))
+            return fail(MGR_ERR_CAPTURE, "auxiliary streams not created and the stream is capturing; call mgr_prepare first");
         MGR_TRY(aux_stream(&aux), "auxiliary stream");
         MGR_TRY(hipEventRecord(aux->start, st), "fork event");
         MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
@@ -1385,7 +1395,15 @@ int mgr_prepare(int dtype, int ndim, const int64_t* shape, const double* const* 
     try {
         g_err.clear();
         Plan* p = nullptr;
-        return get_plan(dtype, ndim, shape, coords, nlevels, nullptr, false, &p);
+        int rc = get_plan(dtype, ndim, shape, coords, nlevels, nullptr, false, &p);
+        if (rc) return rc;
+        // the recomposition's auxiliary streams, so that no stream is created
+        // while a stream is being captured
+        std::lock_guard<std::mutex> lk(g_aux_mu);
+        AuxStream* aux = nullptr;
+        hipError_t e = aux_stream(&aux);
+        if (e != hipSuccess) return hip_fail(e, "auxiliary stream");
+        return MGR_OK;
     } catch (const std::bad_alloc&) {
         return fail(MGR_ERR_ALLOC, "host allocation failed");
     } catch (...) {
