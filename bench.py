@@ -202,7 +202,8 @@ def cpu_baseline(u_sin):
 # passes scaled by the same counters on a copy kernel of known size; valid
 # only while the kernel source matches the one the counters were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_dec_513cube_f32_counters.md")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2007_04457_amd", "csrc", f) for f in ("mgr_stream_dev.h", "mgr_stream.hip")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2007_04457_amd", "csrc", f) for f in (
+    "mgr_internal.h", "mgr_stream_dev.h", "mgr_stream.hip")]
 
 
 def measured_traffic():

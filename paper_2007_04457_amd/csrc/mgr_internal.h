@@ -197,6 +197,19 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
+// Non-temporal stores (cache policy bit 1, "nt"): for whole-line output that
+// nothing in the call reads again.  Keeping such a stream out of the caches
+// spares the next kernel the write-back of its dirty lines.  Stores that
+// leave partial lines must not use them: the caches then stop merging the
+// two halves of a line written by neighbouring workgroups.
+__device__ __forceinline__ void buf_store_nt(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+}
+__device__ __forceinline__ void buf_store_nt(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 2);
+}
 // Workgroup barrier that waits only for this wave's LDS traffic.  HIP's
 // __syncthreads() also drains outstanding global loads, which would stall a
 // register prefetch at every barrier.  Used only where nothing needs global

@@ -332,7 +332,8 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon_al(StreamArgs<T> a)
         const int gr = R0 + rg + 4 * k;
         bool ok;
         const int x = col_of(f, gr, ok);
-        buf_store(v, r, ok ? ((unsigned)gr * cs1 + (unsigned)(C0 + x)) * S : kOut);
+        // the user's output, in whole lines, read by nothing after
+        buf_store_nt(v, r, ok ? ((unsigned)gr * cs1 + (unsigned)(C0 + x)) * S : kOut);
     };
 
     T pW[NCT], pZ[NCT], fo[NRW], fe[NRW];
