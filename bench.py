@@ -222,6 +222,29 @@ def measured_traffic():
     return int(fields["traffic_bytes"].strip())
 
 
+# HBM traffic of all library kernels of one decompose + recompose step, from
+# the same counter runs; valid only while no library source has changed.
+STEP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decompose_recompose_513cube_f32_step_traffic.md")
+CSRC = os.path.join(ROOT, "paper_2007_04457_amd", "csrc")
+
+
+def measured_step_traffic():
+    import hashlib
+    try:
+        text = open(STEP_TRAFFIC_FILE).read()
+        h = hashlib.sha256()
+        for f in sorted(os.listdir(CSRC)):
+            if f.endswith((".h", ".hip", ".cpp")):
+                h.update(open(os.path.join(CSRC, f), "rb").read())
+        src = h.hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("step_bytes", "source_sha256")))
+    if fields.get("source_sha256", "").strip() != src:
+        return None
+    return int(fields["step_bytes"].strip())
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -311,6 +334,15 @@ def main():
         "frac_of_paper_model_peak": round(head["GBps"] / (copy_gbps / 8.43), 4),
         "variants": {f"{k[0]}_{k[1]}": v for k, v in results.items()},
     }
+    step_bytes = measured_step_traffic()
+    out["step_traffic"] = None if step_bytes is None else {
+        # counter-measured bytes of every kernel of the step, as passes over
+        # the field per direction (the paper's design: 8.43) and as a rate
+        # over the measured step time
+        "bytes": step_bytes,
+        "passes_per_direction": round(step_bytes / 2 / (2 * N * 4), 3),
+        "GBps": round(step_bytes / (head["ms_per_step"] * 1e-3) / 1e9, 1),
+        "frac_of_peak": round(step_bytes / (head["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     out.update(extra)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
