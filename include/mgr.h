@@ -114,8 +114,9 @@ const char* mgr_status_string(int status);
 /* Detail of the last error on the calling thread (empty if none). */
 const char* mgr_last_error(void);
 
-/* Frees every cached table, workspace and timing event.  Not safe while
- * work that uses them is still in flight: synchronise first. */
+/* Frees every cached table, workspace and timing event and the
+ * recomposition's streams.  Not safe while work that uses them is still in
+ * flight: synchronise first. */
 void mgr_finalize(void);
 
 /* Level steps whose level grid has at most `max_nodes` nodes run together in

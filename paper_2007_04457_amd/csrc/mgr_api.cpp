@@ -797,6 +797,16 @@ struct AuxStream {
 std::mutex g_aux_mu;
 AuxStream g_aux[64];
 
+void destroy_aux(AuxStream& a)
+{
+    for (hipEvent_t& ev : a.done)
+        if (ev) (void)hipEventDestroy(ev);
+    if (a.start) (void)hipEventDestroy(a.start);
+    if (a.s) (void)hipStreamDestroy(a.s);
+    if (a.s0) (void)hipStreamDestroy(a.s0);
+    a = AuxStream{};
+}
+
 hipError_t aux_stream(AuxStream** out)
 {
     int dev = 0;
@@ -805,16 +815,18 @@ hipError_t aux_stream(AuxStream** out)
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     AuxStream& a = g_aux[dev];
     if (!a.s) {
-        e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
-        if (e != hipSuccess) return e;
-        e = hipStreamCreateWithFlags(&a.s0, hipStreamNonBlocking);
-        if (e != hipSuccess) return e;
-        e = hipEventCreateWithFlags(&a.start, hipEventDisableTiming);
-        if (e != hipSuccess) return e;
-        for (int k = 0; k < kMaxLevels; k++) {
-            e = hipEventCreateWithFlags(&a.done[k], hipEventDisableTiming);
-            if (e != hipSuccess) return e;
+        // built aside and kept only when complete
+        AuxStream n;
+        e = hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.s0, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.start, hipEventDisableTiming);
+        for (int k = 0; k < kMaxLevels && e == hipSuccess; k++)
+            e = hipEventCreateWithFlags(&n.done[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            destroy_aux(n);
+            return e;
         }
+        a = n;
     }
     *out = &a;
     return hipSuccess;
@@ -1467,6 +1479,8 @@ void mgr_finalize(void)
     }
     g_tm.ev.clear();
     g_tm.on = false;
+    std::lock_guard<std::mutex> lk3(g_aux_mu);
+    for (AuxStream& a : g_aux) destroy_aux(a);
 }
 
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes)

@@ -66,3 +66,20 @@ def test_graph_replay_matches_eager(shape, dtype, nu):
         _ = mgr.recompose(mgr.decompose(other, coords), coords)
         torch.cuda.synchronize()
     del graph
+
+
+def test_finalize_then_reuse():
+    """mgr_finalize releases tables, workspaces and the recomposition's
+    streams; later calls rebuild them and give the same results."""
+    shape = (65, 65, 65)
+    u, _ = synth.sinusoid_field(shape, 45)
+    x = torch.from_numpy(u).to(torch.float32).to(DEV)
+    y0 = mgr.decompose(x)
+    r0 = mgr.recompose(y0)
+    torch.cuda.synchronize()
+    mgr.mgr_finalize()
+    y1 = mgr.decompose(x)
+    r1 = mgr.recompose(y1)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert torch.equal(r0, r1)
