@@ -1469,18 +1469,24 @@ const char* mgr_last_error(void) { return g_err.c_str(); }
 
 void mgr_finalize(void)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& kv : g_plans) free_plan(*kv.second);
-    g_plans.clear();
-    std::lock_guard<std::mutex> lk2(g_tm_mu);
+    // one lock at a time: a recomposition holds the stream lock while its
+    // timed launches take the timing lock
+    {
+        std::lock_guard<std::mutex> lk(g_aux_mu);
+        for (AuxStream& a : g_aux) destroy_aux(a);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& kv : g_plans) free_plan(*kv.second);
+        g_plans.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_tm_mu);
     for (auto& e : g_tm.ev) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
     g_tm.ev.clear();
     g_tm.on = false;
-    std::lock_guard<std::mutex> lk3(g_aux_mu);
-    for (AuxStream& a : g_aux) destroy_aux(a);
 }
 
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes)
