@@ -51,6 +51,17 @@ CASES = [
     ((33, 1025), torch.float32, True, -1),
     ((129, 65, 257), torch.float32, True, -1),
     ((257, 17, 33), torch.float64, False, -1),
+    # extreme aspect ratios: one long dimension beside minimal ones
+    ((3, 3, 1025), torch.float32, False, 1),
+    ((1025, 3, 5), torch.float64, True, 1),
+    ((5, 1025, 3), torch.float32, True, 1),
+    ((2049,), torch.float32, True, -1),
+    ((8193,), torch.float64, False, -1),
+    # fibres longer than one workgroup stages (three-phase partitioned
+    # solve): along the contiguous dimension, and along a strided one
+    ((16385,), torch.float64, True, -1),
+    ((32769,), torch.float32, False, -1),
+    ((2049, 3, 3), torch.float32, True, 1),
 ]
 
 
