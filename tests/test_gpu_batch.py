@@ -63,6 +63,29 @@ def test_batch_equals_per_field(dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_batch_long_contiguous_fibres(dtype):
+    """Fibres along the contiguous dimension longer than a batch work item
+    stages (coarse rows of 4097) go through the three-phase partitioned
+    solve as separate waves of items; the per-field path stages them whole,
+    so the two agree to rounding and both match the oracle."""
+    cases = [((8193,), False), ((9, 8193), True), ((17, 9, 33), False)]
+    print(f"\n[batch] long fibres {dtype}", flush=True)
+    xs, coords = make_fields(cases, dtype, 900)
+    plan = mgr.BatchPlan([x.shape for x in xs], dtype, coords)
+    ys = plan.decompose(xs)
+    torch.cuda.synchronize()
+    for i, (x, c) in enumerate(zip(xs, coords)):
+        xd = x.double().cpu().numpy()
+        scale = float(np.max(np.abs(xd)))
+        ref = oracle.decompose(xd, c)
+        got = ys[i].double().cpu().numpy()
+        assert float(np.max(np.abs(got - ref))) / scale <= TOL[dtype], (i, cases[i])
+        per_field = mgr.decompose(x, c).double().cpu().numpy()
+        assert float(np.max(np.abs(got - per_field))) / scale <= TOL[dtype], (i, cases[i])
+    plan.close()
+
+
 def test_batch_repeated_calls_and_levels():
     """Second call with other inputs and partial level counts; every counter
     and the queue start from zero again."""
