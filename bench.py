@@ -249,7 +249,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md but not built", file=sys.stderr)
+              "a multi-GPU path is not built", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2007_04457_amd as mgr
