@@ -83,3 +83,43 @@ def test_finalize_then_reuse():
     torch.cuda.synchronize()
     assert torch.equal(y0, y1)
     assert torch.equal(r0, r1)
+
+
+def test_capture_before_streams_exist_is_refused():
+    """A recomposition captured before the library has its streams (plan
+    built by an eager decomposition after mgr_finalize, no mgr_prepare) is
+    refused with an error before anything is enqueued; after mgr_prepare the
+    same capture replays the eager result."""
+    shape = (65, 65, 65)
+    u, _ = synth.sinusoid_field(shape, 46)
+    x = torch.from_numpy(u).to(torch.float32).to(DEV)
+    torch.cuda.synchronize()
+    mgr.mgr_finalize()
+    y = mgr.decompose(x)
+    torch.cuda.synchronize()
+    r = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g0 = torch.cuda.CUDAGraph()
+    with pytest.raises(mgr.MgrError):
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g0, stream=s):
+                mgr.mgr_recompose(y, r)
+    torch.cuda.synchronize()
+    del g0
+
+    mgr.mgr_prepare(torch.float32, shape)
+    want = mgr.recompose(y)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            mgr.mgr_recompose(y, r)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        r.fill_(float(rep + 5))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(r, want), rep
+    del g
