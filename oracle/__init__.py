@@ -45,6 +45,8 @@ def _load():
         lib.oracle_load_vector_level.restype = ctypes.c_int
         lib.oracle_correction_level.argtypes = [dp, ctypes.c_int, i64p, dpp, ctypes.c_int]
         lib.oracle_correction_level.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         lib.oracle_class_map.argtypes = [ctypes.c_int, i64p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_class_map.restype = ctypes.c_int
@@ -82,6 +84,12 @@ def _check(rc):
 
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def set_threads(n):
+    """Threads for the oracle's loops over independent fibres and nodes
+    (results do not depend on it); returns the previous count."""
+    return _load().oracle_set_threads(int(n))
 
 
 def max_levels(shape):
@@ -146,3 +154,60 @@ def class_map(shape, nlevels=-1):
     _check(lib.oracle_class_map(len(shape), _shape_arg(shape), int(nlevels),
                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
     return out
+
+
+# ---- class-packed layout and progressive recomposition ----------------------
+# The paper's use of the refactored data (Sec. I; Sec. II-A, overall
+# process): coefficient classes are stored and moved separately, and a
+# reader that has only the coarsest classes 0..l reconstructs a lower-
+# fidelity approximation.  The layout here: class 0, then class 1, ...,
+# class L, each a contiguous segment holding its nodes in C order of their
+# grid indices.
+
+
+def class_offsets(shape, nlevels=-1):
+    """Start of each class's segment in the class-packed layout, plus the
+    total: offsets[l] .. offsets[l + 1] hold class l (length L + 2)."""
+    cm = class_map(shape, nlevels)
+    L = max_levels(shape) if nlevels < 0 else nlevels
+    counts = [int(np.count_nonzero(cm == l)) for l in range(L + 1)]
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+
+
+def pack_classes(y, nlevels=-1):
+    """In-place node-order layout -> class-packed layout (a flat array):
+    the values of class 0, then class 1, ..., each in C order (NumPy boolean
+    indexing walks the array in C order)."""
+    y = np.asarray(y)
+    cm = class_map(y.shape, nlevels)
+    L = max_levels(y.shape) if nlevels < 0 else nlevels
+    return np.concatenate([y[cm == l] for l in range(L + 1)])
+
+
+def unpack_classes(p, shape, nlevels=-1):
+    """Class-packed layout -> in-place node-order layout (inverse of
+    pack_classes).  A prefix holding only classes 0..l unpacks with the
+    finer classes set to zero."""
+    p = np.asarray(p)
+    cm = class_map(shape, nlevels)
+    L = max_levels(shape) if nlevels < 0 else nlevels
+    off = class_offsets(shape, nlevels)
+    out = np.zeros(tuple(shape), dtype=p.dtype)
+    for l in range(L + 1):
+        if off[l + 1] <= p.size:
+            out[cm == l] = p[off[l]:off[l + 1]]
+    return out
+
+
+def recompose_level(y, level, coords=None, nlevels=-1):
+    """Progressive recomposition (Sec. II-A, overall process): recompose the
+    refactored array y with every class finer than `level` omitted (set to
+    zero), and return the result at the level-`level` nodes (every index a
+    multiple of 2^(L - level)), i.e. the nodal values of Q_level u."""
+    y = np.asarray(y, dtype=np.float64)
+    L = max_levels(y.shape) if nlevels < 0 else nlevels
+    cm = class_map(y.shape, L)
+    z = np.where(cm <= level, y, 0.0)
+    r = recompose(z, coords, L)
+    s = 2 ** (L - level)
+    return np.ascontiguousarray(r[tuple(slice(None, None, s) for _ in y.shape)])

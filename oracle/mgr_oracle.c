@@ -39,6 +39,19 @@
 
 #define MAXD 4
 
+/* Threads for the loops over independent fibres and nodes (OpenMP when the
+ * library is built with it).  Every element is computed by the same
+ * arithmetic in the same order whatever the thread count, so results are
+ * bitwise independent of it.  Default 1. */
+static int g_threads = 1;
+
+int oracle_set_threads(int n)
+{
+    int prev = g_threads;
+    g_threads = (n < 1) ? 1 : n;
+    return prev;
+}
+
 typedef struct {
     int nd;
     int64_t n[MAXD];     /* full grid sizes */
@@ -125,6 +138,15 @@ static int64_t offset_of(const grid_t* g, const int64_t* j, int k)
     int64_t o = 0;
     for (int d = 0; d < g->nd; d++) o += (j[d] << k) * g->st[d];
     return o;
+}
+
+/* Multi-index j of the C-order flat index idx in a box of sizes m. */
+static void index_of(int nd, int64_t idx, const int64_t* m, int64_t* j)
+{
+    for (int d = nd - 1; d >= 0; d--) {
+        j[d] = idx % m[d];
+        idx /= m[d];
+    }
 }
 
 /* Odometer increment over a box of sizes m; returns 0 when wrapped. */
@@ -217,26 +239,36 @@ static int along_dim(const double* A, double* B, int nd, const int64_t* sh,
     int64_t m_out = (op == OP_MASSTRANS) ? (m_in + 1) / 2
                   : (op == OP_PROLONG_MASS) ? 2 * m_in - 1 : m_in;
     int64_t mx = (m_in > m_out) ? m_in : m_out;
-    double* t0 = (double*)malloc(sizeof(double) * (size_t)mx);
-    double* t1 = (double*)malloc(sizeof(double) * (size_t)mx);
-    int rc = (t0 && t1) ? 0 : 6;
-    for (int64_t o = 0; o < outer && rc == 0; o++) {
-        for (int64_t in = 0; in < inner && rc == 0; in++) {
+    int64_t nfib = outer * inner;
+    int rc = 0;
+    /* every fibre is independent: one per iteration, each thread with its
+     * own two fibre buffers */
+#pragma omp parallel num_threads(g_threads) if (g_threads > 1)
+    {
+        double* t0 = (double*)malloc(sizeof(double) * (size_t)mx);
+        double* t1 = (double*)malloc(sizeof(double) * (size_t)mx);
+        int lrc = (t0 && t1) ? 0 : 6;
+#pragma omp for schedule(static)
+        for (int64_t fb = 0; fb < nfib; fb++) {
+            if (lrc) continue;
+            int64_t o = fb / inner, in = fb % inner;
             for (int64_t j = 0; j < m_in; j++) t0[j] = A[(o * m_in + j) * inner + in];
             if (op == OP_MASSTRANS) {
                 mass_mult(t0, t1, m_in, y);
                 restrict_t(t1, t0, m_in, y);
             } else if (op == OP_SOLVE) {
-                rc = thomas(t0, m_in, y);
+                lrc = thomas(t0, m_in, y);
             } else {
                 prolong(t0, t1, m_out, y);
                 mass_mult(t1, t0, m_out, y);
             }
             for (int64_t i = 0; i < m_out; i++) B[(o * m_out + i) * inner + in] = t0[i];
         }
+        free(t0);
+        free(t1);
+#pragma omp critical
+        if (lrc && !rc) rc = lrc;
     }
-    free(t0);
-    free(t1);
     return rc;
 }
 
@@ -249,16 +281,22 @@ static int along_dim(const double* A, double* B, int nd, const int64_t* sh,
 static int stage_coefficients(double* u, const grid_t* g, int k)
 {
     int nd = g->nd;
-    int64_t m[MAXD], j[MAXD] = {0, 0, 0, 0};
+    int64_t m[MAXD], V = 1;
     double* y[MAXD] = {0};
     int rc = 0;
     for (int d = 0; d < nd; d++) {
         m[d] = lsize(g, d, k);
+        V *= m[d];
         y[d] = level_coords(g, d, k);
         if (!y[d]) rc = 6;
     }
     if (rc == 0) {
-        do {
+        /* each node reads only coarse nodes, which this stage never writes,
+         * so the nodes are independent */
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
+        for (int64_t idx = 0; idx < V; idx++) {
+            int64_t j[MAXD];
+            index_of(nd, idx, m, j);
             int odd[MAXD], t = 0;
             for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
             if (t == 0) continue;
@@ -282,7 +320,7 @@ static int stage_coefficients(double* u, const grid_t* g, int k)
                 interp += w * u[offset_of(g, q, k)];
             }
             u[offset_of(g, j, k)] -= interp;
-        } while (next_index(nd, j, m));
+        }
     }
     for (int d = 0; d < nd; d++) free(y[d]);
     return rc;
@@ -366,16 +404,22 @@ static void stage_apply(double* u, const double* z, const grid_t* g, int k, doub
 static int stage_interpolate_add(double* u, const grid_t* g, int k)
 {
     int nd = g->nd;
-    int64_t m[MAXD], j[MAXD] = {0, 0, 0, 0};
+    int64_t m[MAXD], V = 1;
     double* y[MAXD] = {0};
     int rc = 0;
     for (int d = 0; d < nd; d++) {
         m[d] = lsize(g, d, k);
+        V *= m[d];
         y[d] = level_coords(g, d, k);
         if (!y[d]) rc = 6;
     }
     if (rc == 0) {
-        do {
+        /* each node reads only coarse nodes, which this stage never writes,
+         * so the nodes are independent */
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
+        for (int64_t idx = 0; idx < V; idx++) {
+            int64_t j[MAXD];
+            index_of(nd, idx, m, j);
             int odd[MAXD], t = 0;
             for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
             if (t == 0) continue;
@@ -399,7 +443,7 @@ static int stage_interpolate_add(double* u, const grid_t* g, int k)
                 interp += w * u[offset_of(g, q, k)];
             }
             u[offset_of(g, j, k)] += interp;
-        } while (next_index(nd, j, m));
+        }
     }
     for (int d = 0; d < nd; d++) free(y[d]);
     return rc;

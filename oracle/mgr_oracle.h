@@ -29,6 +29,11 @@ extern "C" {
 
 int oracle_max_levels(int ndim, const int64_t* shape);
 
+/* Threads for the loops over independent fibres and nodes (the library is
+ * built with OpenMP); results are bitwise independent of the count.
+ * Default 1.  Returns the previous value. */
+int oracle_set_threads(int n);
+
 /* Decomposition, Sec. II-A, Eq. (1)-(2): finest to coarsest level. */
 int oracle_decompose(double* u, int ndim, const int64_t* shape,
                      const double* const* coords, int nlevels);

@@ -116,3 +116,27 @@ def progressive_dense(u, coords, L, l0):
     xl, xs = level_coords(shape, coords, 2 ** (L - l0))
     B = kron_all([hat_eval_1d(x, y) for x, y in zip(xs, xl)])
     return (B @ q.reshape(-1)).reshape(shape)
+
+
+def coefficients_dense(u, coords, k):
+    """Coefficient stage of level step k (stride 2^k) alone, Sec. II-A.1:
+    on the level grid, every node that is not a coarse node (some level index
+    odd) becomes u - Pi u, with Pi the multilinear interpolant of the coarse
+    nodes' values (the Kronecker product of 1-D hat-function evaluations);
+    coarse nodes and nodes off the level grid keep their values."""
+    u = np.asarray(u, dtype=np.float64)
+    shape = u.shape
+    out = u.copy()
+    s = 2 ** k
+    xl, _ = level_coords(shape, coords, s)
+    xc = [y[::2] for y in xl]
+    sl = tuple(slice(None, None, s) for _ in shape)
+    v = u[sl]
+    interp = kron_all([hat_eval_1d(y, yc) for y, yc in zip(xl, xc)])
+    pi = (interp @ v[tuple(slice(None, None, 2) for _ in shape)].reshape(-1)).reshape(v.shape)
+    fine = np.zeros(v.shape, dtype=bool)
+    for g in np.meshgrid(*[np.arange(m) for m in v.shape], indexing="ij"):
+        fine |= (g % 2) == 1
+    view = out[sl]
+    view[fine] = (v - pi)[fine]
+    return out

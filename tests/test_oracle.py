@@ -293,6 +293,24 @@ def test_adjoint_finite_difference_17cubed():
         assert abs(fd - an) <= 1e-9 * abs(an), t
 
 
+@pytest.mark.parametrize("shape,k", [((17,), 0), ((33,), 2), ((9, 17), 0), ((17, 9), 1), ((9, 5, 9), 0),
+                                     ((17, 9, 17), 1), ((9, 9, 9), 2)])
+@pytest.mark.parametrize("nonuniform", [False, True])
+def test_coefficients_level_is_u_minus_interpolant(shape, k, nonuniform):
+    """The coefficient stage alone (Sec. II-A.1) at level step k equals
+    u - Pi u at the level grid's fine-only nodes, with Pi assembled densely
+    from hat functions; every other node is unchanged."""
+    rng = np.random.default_rng(hash((shape, k, nonuniform)) % 2**32)
+    coords = rand_coords(rng, shape) if nonuniform else None
+    u = rng.standard_normal(shape)
+    got = oracle.coefficients_level(u, k, coords)
+    want = dense_ref.coefficients_dense(u, coords, k)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(u)), (shape, k)
+    off = np.ones(shape, dtype=bool)
+    off[tuple(slice(None, None, 2 ** k) for _ in shape)] = False
+    assert np.array_equal(got[off], u[off])
+
+
 def test_error_codes():
     u = np.zeros((9, 9))
     with pytest.raises(oracle.OracleError, match="shape"):
@@ -309,3 +327,75 @@ def test_error_codes():
     # nlevels = 0 is the identity
     v = np.arange(81.0).reshape(9, 9)
     assert np.array_equal(oracle.decompose(v, None, 0), v)
+
+
+@pytest.mark.parametrize("shape", [(65, 33, 17), (129, 65), (257,)])
+def test_thread_count_does_not_change_results(shape):
+    """The oracle's loops over independent fibres and nodes give bitwise the
+    same output with 1 and with several threads (decompose, recompose)."""
+    rng = np.random.default_rng(23)
+    coords = rand_coords(rng, shape)
+    u = rng.standard_normal(shape)
+    prev = oracle.set_threads(1)
+    try:
+        d1 = oracle.decompose(u, coords)
+        r1 = oracle.recompose(d1, coords)
+        oracle.set_threads(4)
+        d4 = oracle.decompose(u, coords)
+        r4 = oracle.recompose(d1, coords)
+    finally:
+        oracle.set_threads(prev)
+    assert np.array_equal(d1, d4)
+    assert np.array_equal(r1, r4)
+
+
+
+@pytest.mark.parametrize("shape,L", [((9,), -1), ((17, 9), -1), ((9, 5, 9), -1), ((17, 9, 17), 2), ((5, 5, 5), 0)])
+def test_class_packed_layout_by_brute_force(shape, L):
+    """Class-packed layout: walking the nodes in C order and appending each
+    value to its class's list, then concatenating the lists class 0 first,
+    gives pack_classes; segment lengths follow the nested level grids
+    (class 0: the coarsest grid, class l: level grid l minus level grid
+    l - 1); unpacking inverts it."""
+    rng = np.random.default_rng(31)
+    y = rng.standard_normal(shape)
+    full = oracle.max_levels(shape) if L < 0 else L
+    lists = [[] for _ in range(full + 1)]
+    for idx in np.ndindex(*shape):
+        v = full
+        for i in idx:
+            if i == 0:
+                continue
+            t = 0
+            while i % 2 == 0:
+                i //= 2
+                t += 1
+            v = min(v, t)
+        lists[0 if v >= full else full - v].append(y[idx])
+    want = np.array([x for lst in lists for x in lst])
+    got = oracle.pack_classes(y, L)
+    assert np.array_equal(got, want)
+    sizes = [int(np.prod([(n - 1) // 2 ** (full - l) + 1 for n in shape])) for l in range(full + 1)]
+    counts = [sizes[0]] + [sizes[l] - sizes[l - 1] for l in range(1, full + 1)]
+    assert np.array_equal(oracle.class_offsets(shape, L), np.concatenate([[0], np.cumsum(counts)]))
+    assert np.array_equal(oracle.unpack_classes(got, shape, L), y)
+
+
+@pytest.mark.parametrize("shape", [(17,), (9, 17), (9, 5, 9)])
+@pytest.mark.parametrize("nonuniform", [False, True])
+def test_recompose_level_is_the_projection(shape, nonuniform):
+    """Recomposition from the classes 0..l alone returns the nodal values of
+    the L2 projection Q_l u at the level-l nodes (dense reference), for every
+    l; at l = L it is the input."""
+    rng = np.random.default_rng(37)
+    coords = rand_coords(rng, shape) if nonuniform else None
+    u = rng.standard_normal(shape)
+    L = oracle.max_levels(shape)
+    y = oracle.decompose(u, coords, L)
+    for l in range(L + 1):
+        got = oracle.recompose_level(y, l, coords, L)
+        s = 2 ** (L - l)
+        want = dense_ref.progressive_dense(u, coords, L, l)[tuple(slice(None, None, s) for _ in shape)]
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(u)), l
+    assert np.max(np.abs(oracle.recompose_level(y, L, coords, L) - u)) <= 1e-13 * np.max(np.abs(u))
