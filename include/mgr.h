@@ -8,7 +8,9 @@
  *  - A field is a C-order array of `prod(shape)` elements of type `dtype`
  *    in device memory (HBM), `ndim` in 1..3, `shape[d] = 2^k_d + 1` with
  *    k_d >= 1 (the structured grids of Sec. II-A; shape[ndim-1] is the
- *    contiguous dimension).
+ *    contiguous dimension).  One plane of the array (the contiguous row in
+ *    1-D and 2-D, shape[1] * shape[2] elements in 3-D) must stay below 2 GiB:
+ *    the kernels address within a plane with 32-bit byte offsets.
  *  - `coords` describes node positions (nonuniform structured grids,
  *    Sec. II-A): NULL, or coords[d] == NULL, means uniform spacing along d;
  *    otherwise coords[d] is a HOST array of shape[d] strictly increasing
@@ -53,7 +55,7 @@ typedef enum { MGR_F32 = 0, MGR_F64 = 1 } mgr_dtype;
 enum {
     MGR_OK = 0,
     MGR_ERR_ARG = 1,      /* null pointer, bad ndim or dtype */
-    MGR_ERR_SHAPE = 2,    /* a size is not 2^k + 1 with k >= 1 */
+    MGR_ERR_SHAPE = 2,    /* a size is not 2^k + 1 with k >= 1, or a plane is 2 GiB or more */
     MGR_ERR_LEVELS = 3,   /* nlevels outside -1, 0..min_d k_d */
     MGR_ERR_COORDS = 4,   /* coordinates not strictly increasing or not finite */
     MGR_ERR_HIP = 5,      /* a HIP runtime call or kernel launch failed */
@@ -108,6 +110,46 @@ int mgr_prepare(int dtype, int ndim, const int64_t* shape,
 /* Writes the class id of every node (uint8, C order) to host memory out. */
 int mgr_class_map(int ndim, const int64_t* shape, int nlevels, uint8_t* out);
 
+/* ---- class-packed layout and progressive recomposition -------------------
+ * The paper's use of the refactored data is to store and move coefficient
+ * classes separately and to reconstruct a lower-fidelity approximation from
+ * the coarsest classes alone (Sec. I; Sec. II-A, overall process).
+ *
+ * Class-packed layout: class 0 (the coarsest nodal values), then class 1,
+ * ..., class L, each a contiguous segment holding its nodes in C order of
+ * their grid indices (prod(shape) elements in all).  Class c >= 1 holds the
+ * nodes of level grid c (indices multiples of 2^(L-c)) that are not on level
+ * grid c - 1, so its segment length is |grid c| - |grid c-1|. */
+
+/* Writes the L + 2 segment starts of the class-packed layout to the host
+ * array offsets: class c occupies [offsets[c], offsets[c+1]), and
+ * offsets[L+1] = prod(shape). */
+int mgr_class_offsets(int ndim, const int64_t* shape, int nlevels, int64_t* offsets);
+
+/* dst (class-packed) <- src (in-place node order), a permutation of the
+ * elements; out of place (src != dst), device pointers, asynchronous on
+ * `stream`. */
+int mgr_pack_classes(const void* src, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+                     void* stream);
+
+/* dst (in-place node order) <- src (class-packed): the inverse permutation. */
+int mgr_unpack_classes(const void* src, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+                       void* stream);
+
+/* Progressive recomposition: dst <- the nodal values of Q_level u (the L2
+ * projection onto level `level`, Eq. (1)) at the level-`level` nodes, an
+ * array of shape (shape[d] - 1) / 2^(L - level) + 1, from the classes
+ * 0..level of a refactored array src; classes finer than `level` are never
+ * read.  packed = 0: src is the in-place layout (prod(shape) elements);
+ * packed = 1: src is the class-packed layout, of which only the first
+ * offsets[level + 1] elements are read (a prefix holding just those classes
+ * is enough).  level = L gives the full recomposition.  Uses the cached
+ * plan of the level-`level` grid (prepare it like any problem before graph
+ * capture: mgr_prepare on that shape, coordinates x[::2^(L-level)] and
+ * `level` levels). */
+int mgr_recompose_level(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                        const double* const* coords, int nlevels, int level, int packed, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* mgr_status_string(int status);
 
@@ -138,11 +180,15 @@ int64_t mgr_set_tail_max_nodes(int64_t max_nodes);
  * partitions side by side, Sec. IV-C); the autotuner follows its
  * model-then-measure tuning of launch shapes (Sec. III-C).
  *
- * Ownership: the plan owns its tables, per-field workspaces and a pinned
- * staging buffer for the data pointers; all are allocated by
- * mgr_batch_plan_create (synchronously), so mgr_batch_decompose allocates
- * nothing and may be captured into a HIP graph.  A captured graph replays
- * with the pointers of the call that was captured. */
+ * Ownership: the plan owns its tables (its own copies, untouched by
+ * mgr_finalize), per-field workspaces and a device table of data pointers;
+ * all are allocated by mgr_batch_plan_create (synchronously), so
+ * mgr_batch_decompose allocates nothing and may be captured into a HIP
+ * graph.  Each call writes its src/dst pointers into the plan's table with
+ * small kernels that carry them as launch arguments, so a captured graph
+ * replays with the pointers of the call that was captured, whatever eager
+ * calls ran in between; calls and replays on one plan share its workspace
+ * and must be ordered on one stream. */
 typedef struct mgr_batch_plan mgr_batch_plan;
 
 /* Plans a batch of nfields fields: field f has ndim[f] dimensions, sizes
@@ -170,7 +216,7 @@ int mgr_batch_config(const mgr_batch_plan* plan, int* chunk, int* launches, int6
 /* Sets the chunk length (1..128) and rebuilds the work items. */
 int mgr_batch_set_config(mgr_batch_plan* plan, int chunk);
 
-/* Frees the plan (after synchronising with its last upload). */
+/* Frees the plan (hipFree waits for work still using it). */
 void mgr_batch_plan_destroy(mgr_batch_plan* plan);
 
 /* ---- measurement support ------------------------------------------------

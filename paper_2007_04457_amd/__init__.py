@@ -12,15 +12,18 @@ taking ``src`` and ``dst`` tensors), with out-of-place conveniences
 (``decompose`` ...), an autograd function (``Decompose``) and the batched
 work-queue decomposition (``BatchPlan``, over ``mgr_batch_*``).
 """
+import numpy as np
+
 from . import _lib
 from ._lib import MgrError, MGR_F32, MGR_F64
 
 __all__ = [
     "MgrError", "MGR_F32", "MGR_F64",
     "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_prepare",
-    "mgr_class_map", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
+    "mgr_class_map", "class_masks", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
     "decompose", "recompose", "decompose_adjoint", "Decompose", "kernel_classes", "BatchPlan",
+    "class_offsets", "pack_classes", "unpack_classes", "recompose_level",
 ]
 
 
@@ -102,6 +105,87 @@ def mgr_class_map(shape, nlevels=-1):
     lib = _lib.load()
     _lib.check(lib.mgr_class_map(len(shape), _lib.shape_arg(shape), int(nlevels),
                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return out
+
+
+def class_masks(shape, nlevels=-1, device=None):
+    """One boolean mask per coefficient class of the refactored layout:
+    masks[l] is True at the nodes holding class l (0 = the coarsest nodal
+    values, L = the finest coefficients), from mgr_class_map.  NumPy arrays,
+    or torch tensors on `device` when given."""
+    cm = mgr_class_map(shape, nlevels)
+    L = mgr_max_levels(shape) if int(nlevels) < 0 else int(nlevels)
+    masks = [cm == l for l in range(L + 1)]
+    if device is None:
+        return masks
+    torch = _torch()
+    return [torch.from_numpy(m).to(device) for m in masks]
+
+
+def class_offsets(shape, nlevels=-1):
+    """Segment starts of the class-packed layout (L + 2 int64 values):
+    class c occupies [offsets[c], offsets[c + 1])."""
+    import ctypes
+    import numpy as np
+    L = mgr_max_levels(shape) if int(nlevels) < 0 else int(nlevels)
+    out = np.zeros(L + 2, dtype=np.int64)
+    _lib.check(_lib.load().mgr_class_offsets(len(shape), _lib.shape_arg(shape), int(nlevels),
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
+def _pack_call(name, src, dst, shape, nlevels):
+    _check(src, "src")
+    _check(dst, "dst")
+    if src.numel() != dst.numel() or src.dtype != dst.dtype or src.device != dst.device:
+        raise ValueError("src and dst must have the same size, dtype and device")
+    torch = _torch()
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    with torch.cuda.device(src.device):
+        st = getattr(_lib.load(), name)(src.data_ptr(), dst.data_ptr(), _dtype_code(src), len(shape),
+                                        _lib.shape_arg(shape), int(nlevels), stream)
+    _lib.check(st)
+    return dst
+
+
+def pack_classes(y, nlevels=-1, out=None):
+    """Class-packed layout (a flat tensor) of the refactored array y."""
+    if out is None:
+        out = _torch().empty(y.numel(), dtype=y.dtype, device=y.device)
+    return _pack_call("mgr_pack_classes", y, out, tuple(y.shape), nlevels)
+
+
+def unpack_classes(p, shape, nlevels=-1, out=None):
+    """In-place layout of shape `shape` from a class-packed tensor p."""
+    if out is None:
+        out = _torch().empty(tuple(shape), dtype=p.dtype, device=p.device)
+    return _pack_call("mgr_unpack_classes", p, out, tuple(shape), nlevels)
+
+
+def recompose_level(src, level, shape=None, coords=None, nlevels=-1, packed=False, out=None):
+    """Progressive recomposition: the nodal values of Q_level u on the
+    level-`level` grid, from the classes 0..level of a refactored array
+    (in-place layout of shape `shape`, or a class-packed tensor, of which a
+    prefix of offsets[level + 1] elements is enough)."""
+    torch = _torch()
+    shape = tuple(src.shape) if shape is None else tuple(int(n) for n in shape)
+    L = mgr_max_levels(shape) if int(nlevels) < 0 else int(nlevels)
+    sub = tuple((n - 1) // 2 ** (L - level) + 1 for n in shape)
+    if out is None:
+        out = torch.empty(sub, dtype=src.dtype, device=src.device)
+    _check(src, "src")
+    _check(out, "out")
+    need = int(np.prod(shape)) if not packed else int(class_offsets(shape, nlevels)[min(level, L) + 1])
+    if src.numel() < need or tuple(out.shape) != sub or out.dtype != src.dtype:
+        raise ValueError("src too small, or out of the wrong shape or dtype")
+    cp, keep = _lib.coords_arg(shape, coords)
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    with torch.cuda.device(src.device):
+        st = _lib.load().mgr_recompose_level(src.data_ptr(), out.data_ptr(), _dtype_code(src), len(shape),
+                                             _lib.shape_arg(shape), cp, int(nlevels), int(level),
+                                             1 if packed else 0, stream)
+    del keep
+    _lib.check(st)
     return out
 
 

@@ -46,6 +46,15 @@ def load():
     lib.mgr_prepare.restype = ctypes.c_int
     lib.mgr_class_map.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
     lib.mgr_class_map.restype = ctypes.c_int
+    lib.mgr_class_offsets.argtypes = [ctypes.c_int, i64p, ctypes.c_int, i64p]
+    lib.mgr_class_offsets.restype = ctypes.c_int
+    for name in ("mgr_pack_classes", "mgr_unpack_classes"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int, vp]
+        fn.restype = ctypes.c_int
+    lib.mgr_recompose_level.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, vp]
+    lib.mgr_recompose_level.restype = ctypes.c_int
     lib.mgr_status_string.argtypes = [ctypes.c_int]
     lib.mgr_status_string.restype = ctypes.c_char_p
     lib.mgr_last_error.argtypes = []

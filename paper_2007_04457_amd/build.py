@@ -1,18 +1,24 @@
-"""Builds libmgr.so (the gfx950 HIP library behind include/mgr.h) in-tree."""
+"""Builds libmgr.so (the gfx950 HIP library behind include/mgr.h) in-tree.
+
+Each source compiles to its own object in `_build/` (in parallel), then one
+link step writes libmgr.so.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgr.so")
+OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("mgr_api.cpp", "mgr_kernels.hip", "mgr_stream.hip", "mgr_recon.hip", "mgr_solve.hip", "mgr_tail.hip",
-            "mgr_batch.hip", "mgr_adjoint.hip")]
+            "mgr_batch.hip", "mgr_adjoint.hip", "mgr_packed.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-command-line-argument",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -20,8 +26,22 @@ FLAGS = [
 ]
 
 
+def _compile(src, verbose):
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    lang = ["-x", "hip"] if src.endswith(".cpp") else []
+    cmd = [HIPCC] + FLAGS + lang + ["-c", "-o", obj, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp"] + SOURCES
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

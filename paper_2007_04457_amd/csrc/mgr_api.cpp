@@ -135,6 +135,16 @@ int validate(int dtype, int ndim, const int64_t* shape, const double* const* coo
                                            std::to_string(shape[d]) + " is not 2^k+1 with k >= 1");
         kmin = std::min(kmin, k);
     }
+    // The kernels address within one plane of the array (the contiguous row
+    // in 1-D and 2-D, a dim-1 x dim-2 plane in 3-D) with 32-bit byte offsets,
+    // and mark lanes off the grid with an offset of 2^31.
+    {
+        const int64_t esz = (dtype == MGR_F64) ? 8 : 4;
+        const int64_t plane = (ndim == 3) ? shape[1] * shape[2] : shape[ndim - 1];
+        if (plane > ((int64_t)1 << 31) / esz - 1)
+            return fail(MGR_ERR_SHAPE, "a plane of " + std::to_string(plane) + " elements exceeds the kernels' "
+                                       "2 GiB per-plane addressing");
+    }
     if (*nlevels == -1) *nlevels = kmin - 1;
     if (*nlevels < 0 || *nlevels > kmin)
         return fail(MGR_ERR_LEVELS, "nlevels = " + std::to_string(*nlevels) + " outside 0.." +
@@ -352,14 +362,18 @@ void push_table(std::vector<T>& buf, const std::vector<double>& v, size_t* off)
     while (buf.size() % 64) buf.push_back(T(0));
 }
 
+// Host half of a plan: the level layouts, the tables in the working
+// precision (into `host`) and the workspace layout, without touching the
+// device.  `dec_only` leaves out the buffers that only recomposition and the
+// adjoint use.
 template <typename T>
-int build_plan(Plan& p, const double* const* coords)
+void plan_layout(Plan& p, const double* const* coords, bool dec_only, std::vector<T>& host)
 {
     const int L = p.nlevels;
     std::vector<std::vector<double>> X(3);
     for (int d = 0; d < 3; d++)
         if (p.active[d]) X[d] = axis_positions(p.n[d], coords ? coords[p.udim[d]] : nullptr);
-    std::vector<T> host;
+    host.clear();
     p.lv.resize((size_t)L);
     for (int k = 0; k < L; k++) {
         LevelLayout& ly = p.lv[(size_t)k];
@@ -438,7 +452,7 @@ int build_plan(Plan& p, const double* const* coords)
     off = align_up(off + (L > 1 ? (size_t)v1 : 0), al);
     p.Zrec.assign((size_t)L, 0);
     for (int k = 0; k < L; k++) {
-        if (k < 2) {
+        if (k < 2 || dec_only) {
             p.Zrec[(size_t)k] = (k == 0) ? p.F : p.F2;
             continue;
         }
@@ -447,13 +461,20 @@ int build_plan(Plan& p, const double* const* coords)
         p.Zrec[(size_t)k] = off;
         off = align_up(off + (size_t)v, al);
     }
-    p.Tb = off; off = align_up(off + (L > 0 ? (size_t)V0 : 0), al);
+    p.Tb = off; off = align_up(off + (L > 0 && !dec_only ? (size_t)V0 : 0), al);
     p.Yb = off; off = align_up(off + 2 * Fn / kSeg + 64, al);
-    p.Yb2 = off; off = align_up(off + (L > 1 ? 2 * (size_t)v1 / kSeg + 64 : 0), al);
+    p.Yb2 = off; off = align_up(off + (L > 1 && !dec_only ? 2 * (size_t)v1 / kSeg + 64 : 0), al);
     p.esize = sizeof(T);
     p.ws_bytes = off * sizeof(T);
     p.tables_bytes = host.size() * sizeof(T);
-    if (p.ws_bytes + p.tables_bytes > workspace_cap())
+}
+
+template <typename T>
+int build_plan(Plan& p, const double* const* coords, bool with_ws)
+{
+    std::vector<T> host;
+    plan_layout<T>(p, coords, false, host);
+    if ((with_ws ? p.ws_bytes : 0) + p.tables_bytes > workspace_cap())
         return fail(MGR_ERR_ALLOC, "workspace of " + std::to_string(p.ws_bytes) +
                                        " bytes exceeds MGR_WORKSPACE_MAX");
     if (p.tables_bytes) {
@@ -462,7 +483,7 @@ int build_plan(Plan& p, const double* const* coords)
         e = hipMemcpy(p.tables, host.data(), p.tables_bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload tables");
     }
-    if (p.ws_bytes) {
+    if (with_ws && p.ws_bytes) {
         hipError_t e = hipMalloc(&p.ws, p.ws_bytes);
         if (e != hipSuccess) {
             p.ws = nullptr;
@@ -477,6 +498,30 @@ void free_plan(Plan& p)
     if (p.tables) (void)hipFree(p.tables);
     if (p.ws) (void)hipFree(p.ws);
     p.tables = p.ws = nullptr;
+}
+
+int new_plan(int dev, int dtype, int ndim, const int64_t* shape, const double* const* coords, int nlevels,
+             bool with_ws, std::unique_ptr<Plan>& out);
+
+// Problem dimensions of a plan (validated arguments): 3-D as (n0, n1, n2);
+// 2-D as (n0, 1, n1) so the streaming kernel walks rows; 1-D as (1, 1, n0).
+void plan_dims(Plan& p, int dev, int dtype, int ndim, const int64_t* shape, int nlevels)
+{
+    p.device = dev;
+    p.dtype = dtype;
+    p.ndim = ndim;
+    p.nlevels = nlevels;
+    static const int kMap[4][3] = {{-1, -1, -1}, {-1, -1, 0}, {0, -1, 1}, {0, 1, 2}};
+    for (int d = 0; d < 3; d++) {
+        p.udim[d] = kMap[ndim][d];
+        if (p.udim[d] >= 0) {
+            p.n[d] = shape[p.udim[d]];
+            p.active[d] = true;
+        }
+    }
+    p.st[2] = 1;
+    p.st[1] = p.n[2];
+    p.st[0] = p.n[1] * p.n[2];
 }
 
 int get_plan(int dtype, int ndim, const int64_t* shape, const double* const* coords,
@@ -496,31 +541,27 @@ int get_plan(int dtype, int ndim, const int64_t* shape, const double* const* coo
     }
     if (check_capture && capturing(st))
         return fail(MGR_ERR_CAPTURE, "problem not prepared and the stream is capturing; call mgr_prepare first");
+    std::unique_ptr<Plan> p;
+    rc = new_plan(dev, dtype, ndim, shape, coords, nlevels, true, p);
+    if (rc) return rc;
+    *out = p.get();
+    g_plans.emplace(key, std::move(p));
+    return MGR_OK;
+}
+
+// A plan of a validated problem: tables uploaded and, with `with_ws`, its
+// workspace allocated.
+int new_plan(int dev, int dtype, int ndim, const int64_t* shape, const double* const* coords, int nlevels,
+             bool with_ws, std::unique_ptr<Plan>& out)
+{
     auto p = std::make_unique<Plan>();
-    p->device = dev;
-    p->dtype = dtype;
-    p->ndim = ndim;
-    p->nlevels = nlevels;
-    // 3-D: (n0, n1, n2); 2-D: (n0, 1, n1) so the streaming kernel walks
-    // rows; 1-D: (1, 1, n0).
-    static const int kMap[4][3] = {{-1, -1, -1}, {-1, -1, 0}, {0, -1, 1}, {0, 1, 2}};
-    for (int d = 0; d < 3; d++) {
-        p->udim[d] = kMap[ndim][d];
-        if (p->udim[d] >= 0) {
-            p->n[d] = shape[p->udim[d]];
-            p->active[d] = true;
-        }
-    }
-    p->st[2] = 1;
-    p->st[1] = p->n[2];
-    p->st[0] = p->n[1] * p->n[2];
-    rc = (dtype == MGR_F32) ? build_plan<float>(*p, coords) : build_plan<double>(*p, coords);
+    plan_dims(*p, dev, dtype, ndim, shape, nlevels);
+    int rc = (dtype == MGR_F32) ? build_plan<float>(*p, coords, with_ws) : build_plan<double>(*p, coords, with_ws);
     if (rc) {
         free_plan(*p);
         return rc;
     }
-    *out = p.get();
-    g_plans.emplace(key, std::move(p));
+    out = std::move(p);
     return MGR_OK;
 }
 
@@ -654,6 +695,7 @@ int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = 
 }
 
 View3 full_view(const Plan& p) { return packed(p.n); }
+View3 packed_view3(const int64_t* n) { return packed(n); }
 
 template <typename T>
 int identity_copy(const Plan& p, const void* src, void* dst, hipStream_t st)
@@ -987,20 +1029,19 @@ constexpr int kMaxBatchChunk = 128;  // coarse planes per streaming item (the ke
 
 struct BatchPlan {
     int dtype = 0, nfields = 0, device = 0;
-    std::vector<Plan*> plans;
+    // per-field plans built for the batch alone (tables only; the batch's
+    // workspace replaces theirs), so the cache and mgr_finalize never touch them
+    std::vector<std::unique_ptr<Plan>> plans;
     std::vector<int> kt;           // first tail level step per field
     std::vector<size_t> wsoff;     // byte offset of each field's workspace
     void* ws = nullptr;            // the fields' workspaces (same layout as their plans')
     void* dev = nullptr;           // device tables (one allocation)
-    void* host_ptrs = nullptr;     // pinned staging of the per-call pointers
     size_t off_items = 0, off_sargs = 0, off_solves = 0, off_scat = 0, off_tail = 0, off_tailf = 0, off_ptrs = 0,
            off_args = 0, dev_bytes = 0;
     std::vector<std::pair<int, int>> waves;  // (first item, items) per launch
     int n_items = 0, n_tail = 0;
     int chunk = 8, tuned = 0;
     int64_t bytes = 0;             // input bytes of the batch
-    hipEvent_t staged = nullptr;   // the pointer upload of the last call
-    bool staged_pending = false;
 };
 
 template <typename T>
@@ -1228,8 +1269,8 @@ void free_batch(BatchPlan* b)
     if (!b) return;
     if (b->dev) (void)hipFree(b->dev);
     if (b->ws) (void)hipFree(b->ws);
-    if (b->host_ptrs) (void)hipHostFree(b->host_ptrs);
-    if (b->staged) (void)hipEventDestroy(b->staged);
+    for (auto& p : b->plans)
+        if (p) free_plan(*p);
     delete b;
 }
 
@@ -1237,23 +1278,17 @@ template <typename T>
 int batch_run(BatchPlan& b, const void* const* src, void* const* dst, hipStream_t st)
 {
     const int nf = b.nfields;
-    const bool cap = capturing(st);
-    if (b.staged_pending && !cap) {
-        // the previous call's upload must have read the staging buffer
-        hipError_t e = hipEventSynchronize(b.staged);
-        if (e != hipSuccess) return hip_fail(e, "batch staging");
-    }
-    void** hp = (void**)b.host_ptrs;
-    for (int f = 0; f < nf; f++) {
-        hp[f] = const_cast<void*>(src[f]);
-        hp[nf + f] = dst[f];
-    }
     char* d = (char*)b.dev;
-    MGR_TRY(hipMemcpyAsync(d + b.off_ptrs, hp, 2 * sizeof(void*) * (size_t)nf, hipMemcpyHostToDevice, st),
-            "batch pointer upload");
-    if (!cap) {
-        MGR_TRY(hipEventRecord(b.staged, st), "batch staging event");
-        b.staged_pending = true;
+    // the call's pointers (src then dst) travel as kernel arguments
+    for (int i0 = 0; i0 < 2 * nf; i0 += kPtrChunk) {
+        PtrChunk c;
+        c.first = i0;
+        c.n = std::min(kPtrChunk, 2 * nf - i0);
+        for (int i = 0; i < c.n; i++) {
+            const int j = i0 + i;
+            c.p[i] = (j < nf) ? const_cast<void*>(src[j]) : dst[j - nf];
+        }
+        MGR_TRY(launch_set_ptrs(c, (void**)(d + b.off_ptrs), st), "batch pointer upload");
     }
     const BatchKernelArgs<T>* dev_args = (const BatchKernelArgs<T>*)(d + b.off_args);
     for (size_t w = 0; w < b.waves.size(); w++) {
@@ -1283,36 +1318,29 @@ int batch_create(int nfields, const int* ndim, const int64_t* const* shapes, con
     b->nfields = nfields;
     size_t ws_total = 0;
     const size_t esz = (dtype == MGR_F64) ? 8 : 4;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     for (int f = 0; f < nfields; f++) {
-        Plan* p = nullptr;
-        int rc = get_plan(dtype, ndim[f], shapes[f], coords ? coords[f] : nullptr, nlevels ? nlevels[f] : -1, nullptr,
-                          false, &p);
+        std::unique_ptr<Plan> pp;
+        int nl = nlevels ? nlevels[f] : -1;
+        const double* const* cf = coords ? coords[f] : nullptr;
+        int rc = validate(dtype, ndim ? ndim[f] : 0, shapes[f], cf, &nl);
+        if (rc == MGR_OK) rc = new_plan(b->device, dtype, ndim[f], shapes[f], cf, nl, false, pp);
         if (rc) return fail(rc, "field " + std::to_string(f) + ": " + g_err);
+        Plan* p = pp.get();
+        b->plans.push_back(std::move(pp));
         if (p->nlevels == 0) return fail(MGR_ERR_LEVELS, "field " + std::to_string(f) + ": batches need nlevels >= 1");
         const int kt = tail_start(*p);  // as the per-field path, so results agree bit for bit
-        b->plans.push_back(p);
         b->kt.push_back(kt);
         b->wsoff.push_back(ws_total);
         ws_total = align_up(ws_total + p->ws_bytes, 256);
         b->bytes += (int64_t)(p->n[0] * p->n[1] * p->n[2]) * (int64_t)esz;
     }
     if (ws_total > workspace_cap()) return fail(MGR_ERR_ALLOC, "batch workspace exceeds MGR_WORKSPACE_MAX");
-    hipError_t e = hipGetDevice(&b->device);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     e = hipMalloc(&b->ws, std::max<size_t>(ws_total, 256));
     if (e != hipSuccess) {
         b->ws = nullptr;
         return fail(MGR_ERR_ALLOC, std::string("hipMalloc batch workspace: ") + hipGetErrorString(e));
-    }
-    e = hipHostMalloc(&b->host_ptrs, 2 * sizeof(void*) * (size_t)nfields, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        b->host_ptrs = nullptr;
-        return fail(MGR_ERR_ALLOC, std::string("hipHostMalloc: ") + hipGetErrorString(e));
-    }
-    e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        b->staged = nullptr;
-        return hip_fail(e, "hipEventCreate");
     }
     int rc = (dtype == MGR_F64) ? batch_upload<double>(*b, 8) : batch_upload<float>(*b, 8);
     if (rc) return rc;
@@ -1351,7 +1379,112 @@ double batch_model_us(const BatchPlan& b, int chunk)
     return bytes / bw + t_item * items / (4.0 * device_cu_count());
 }
 
+// ---- class-packed layout and progressive recomposition --------------------
+// Segment starts of the class-packed layout: class 0 is the level-0 grid,
+// class c the level-c grid minus the level-(c-1) grid (paper levels, L
+// finest); level grid c has stride 2^(L - c).
+void class_offsets_of(int ndim, const int64_t* shape, int L, int64_t* off)
+{
+    auto grid = [&](int c) {
+        int64_t v = 1;
+        for (int d = 0; d < ndim; d++) v *= ((shape[d] - 1) >> (L - c)) + 1;
+        return v;
+    };
+    off[0] = 0;
+    off[1] = grid(0);
+    for (int c = 1; c <= L; c++) off[c + 1] = off[c] + grid(c) - grid(c - 1);
+}
+
+PackArgs pack_args(int ndim, const int64_t* shape, int L)
+{
+    Plan p;
+    plan_dims(p, 0, MGR_F32, ndim, shape, L);
+    PackArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int d = 0; d < 3; d++) a.n[d] = p.n[d];
+    a.L = L;
+    class_offsets_of(ndim, shape, L, a.off);
+    return a;
+}
+
+int run_pack(bool pack, const void* src, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+             void* stream)
+{
+    if (!src || !dst) return fail(MGR_ERR_ARG, "src or dst is NULL");
+    if (src == dst) return fail(MGR_ERR_ARG, "the class-packed layout is formed out of place");
+    int rc = validate(dtype, ndim, shape, nullptr, &nlevels);
+    if (rc) return rc;
+    if (nlevels > kMaxClassLevels) return fail(MGR_ERR_LEVELS, "too many levels for the class-packed layout");
+    const PackArgs a = pack_args(ndim, shape, nlevels);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = (dtype == MGR_F32) ? launch_pack<float>((const float*)src, (float*)dst, a, pack, st)
+                                      : launch_pack<double>((const double*)src, (double*)dst, a, pack, st);
+    return e == hipSuccess ? MGR_OK : hip_fail(e, "pack launch");
+}
+
+// Recomposition from the classes 0..level: the level grid `level` (stride
+// s = 2^(L - level)) with its classes is the refactored array of the same
+// method on that grid (shape (n - 1) / s + 1, coordinates x[::s], `level`
+// level steps: the decomposition's coarser steps only ever see it), so it is
+// gathered into the sub-problem's spare buffer (from the strided in-place
+// array, or by unpacking the class-packed prefix, which is the sub-problem's
+// own class-packed layout) and recomposed by the sub-problem's plan.
+template <typename T>
+int run_recompose_level(const void* src_, void* dst_, int ndim, const int64_t* shape, const double* const* coords,
+                        int L, int level, bool packed, hipStream_t st)
+{
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    const int sh = L - level;
+    int64_t sub[3] = {1, 1, 1};
+    for (int d = 0; d < ndim; d++) sub[d] = ((shape[d] - 1) >> sh) + 1;
+    Plan full;
+    plan_dims(full, 0, sizeof(T) == 8 ? MGR_F64 : MGR_F32, ndim, shape, L);
+    View3 sv;  // the level grid inside the in-place array
+    for (int d = 0; d < 3; d++) {
+        sv.n[d] = full.active[d] ? ((full.n[d] - 1) >> sh) + 1 : 1;
+        sv.s[d] = full.st[d] << sh;
+    }
+    if (level == 0) {
+        // the coarsest values: the strided grid, or the first segment
+        if (packed) {
+            const size_t bytes = (size_t)(sv.n[0] * sv.n[1] * sv.n[2]) * sizeof(T);
+            MGR_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st), "copy");
+        } else {
+            MGR_TRY(launch_copy_view<T>(src, nullptr, sv, dst, packed_view3(sv.n), st), "gather");
+        }
+        return MGR_OK;
+    }
+    std::vector<std::vector<double>> cs;
+    std::vector<const double*> cp;
+    if (coords) {
+        cs.resize((size_t)ndim);
+        for (int d = 0; d < ndim; d++) {
+            if (!coords[d]) {
+                cp.push_back(nullptr);
+                continue;
+            }
+            for (int64_t i = 0; i < sub[d]; i++) cs[(size_t)d].push_back(coords[d][i << sh]);
+            cp.push_back(cs[(size_t)d].data());
+        }
+    }
+    Plan* ps = nullptr;
+    int rc = get_plan(sizeof(T) == 8 ? MGR_F64 : MGR_F32, ndim, sub, coords ? cp.data() : nullptr, level, st, true,
+                      &ps);
+    if (rc) return rc;
+    T* tmp = (T*)ps->ws + ps->Tb;  // the adjoint's buffer: unused by recomposition
+    if (packed) {
+        const PackArgs a = pack_args(ndim, sub, level);
+        MGR_TRY(launch_pack<T>(src, tmp, a, false, st), "unpack launch");
+    } else {
+        MGR_TRY(launch_copy_view<T>(src, nullptr, sv, tmp, packed_view3(sv.n), st), "gather");
+    }
+    return run_recompose<T>(*ps, tmp, dst, st);
+}
+
 }  // namespace
+
+
 }  // namespace mgr
 
 using namespace mgr;
@@ -1416,6 +1549,61 @@ int mgr_prepare(int dtype, int ndim, const int64_t* shape, const double* const* 
         hipError_t e = aux_stream(&aux);
         if (e != hipSuccess) return hip_fail(e, "auxiliary stream");
         return MGR_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_class_offsets(int ndim, const int64_t* shape, int nlevels, int64_t* offsets)
+{
+    g_err.clear();
+    if (!offsets) return fail(MGR_ERR_ARG, "offsets is NULL");
+    int rc = validate(MGR_F32, ndim, shape, nullptr, &nlevels);
+    if (rc) return rc;
+    class_offsets_of(ndim, shape, nlevels, offsets);
+    return MGR_OK;
+}
+
+int mgr_pack_classes(const void* src, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+                     void* stream)
+{
+    try {
+        g_err.clear();
+        return run_pack(true, src, dst, dtype, ndim, shape, nlevels, stream);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_unpack_classes(const void* src, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+                       void* stream)
+{
+    try {
+        g_err.clear();
+        return run_pack(false, src, dst, dtype, ndim, shape, nlevels, stream);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_recompose_level(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                        const double* const* coords, int nlevels, int level, int packed, void* stream)
+{
+    try {
+        g_err.clear();
+        if (!src || !dst) return fail(MGR_ERR_ARG, "src or dst is NULL");
+        if (src == dst) return fail(MGR_ERR_ARG, "progressive recomposition is out of place");
+        int rc = validate(dtype, ndim, shape, coords, &nlevels);
+        if (rc) return rc;
+        if (level < 0 || level > nlevels)
+            return fail(MGR_ERR_LEVELS, "level = " + std::to_string(level) + " outside 0.." + std::to_string(nlevels));
+        if (packed != 0 && packed != 1) return fail(MGR_ERR_ARG, "packed must be 0 or 1");
+        hipStream_t st = (hipStream_t)stream;
+        return (dtype == MGR_F32)
+                   ? run_recompose_level<float>(src, dst, ndim, shape, coords, nlevels, level, packed != 0, st)
+                   : run_recompose_level<double>(src, dst, ndim, shape, coords, nlevels, level, packed != 0, st);
     } catch (const std::bad_alloc&) {
         return fail(MGR_ERR_ALLOC, "host allocation failed");
     } catch (...) {
@@ -1667,8 +1855,7 @@ void mgr_batch_plan_destroy(mgr_batch_plan* plan)
 {
     BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
     if (!b) return;
-    if (b->staged_pending) (void)hipEventSynchronize(b->staged);
-    free_batch(b);
+    free_batch(b);  // hipFree waits for work still using the memory
 }
 
 }  // extern "C"

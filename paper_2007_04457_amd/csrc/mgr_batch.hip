@@ -177,6 +177,21 @@ hipError_t launch_batch_wave(const BatchKernelArgs<T>* dev_a, int first, int n, 
     return hipGetLastError();
 }
 
+// Writes up to kPtrChunk pointers, passed by value, to dst.  A graph that
+// captures the launch keeps the values in its kernel node, so each replay
+// restores the pointers of the call that was captured, whatever calls ran
+// in between.
+__global__ void __launch_bounds__(64) k_set_ptrs(PtrChunk c, void** dst)
+{
+    for (int i = (int)threadIdx.x; i < c.n; i += 64) dst[c.first + i] = c.p[i];
+}
+
+hipError_t launch_set_ptrs(const PtrChunk& c, void** dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, st, c, dst);
+    return hipGetLastError();
+}
+
 template hipError_t launch_batch_wave<float>(const BatchKernelArgs<float>*, int, int, hipStream_t);
 template hipError_t launch_batch_wave<double>(const BatchKernelArgs<double>*, int, int, hipStream_t);
 

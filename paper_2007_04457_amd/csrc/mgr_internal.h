@@ -287,6 +287,15 @@ struct BatchKernelArgs {
 constexpr int kThreadsBatch = 256;
 constexpr int kBatchRowSpan = 4096;
 
+// Per-call data pointers of a batch, uploaded by kernel arguments (kPtrChunk
+// per launch): entries first .. first + n - 1 of the device pointer table.
+constexpr int kPtrChunk = 128;
+struct PtrChunk {
+    void* p[kPtrChunk];
+    int first, n;
+};
+hipError_t launch_set_ptrs(const PtrChunk& c, void** dst, hipStream_t st);
+
 // Runs items [first, first + n) of the table dev_a->items, one workgroup each.
 template <typename T>
 hipError_t launch_batch_wave(const BatchKernelArgs<T>* dev_a, int first, int n, hipStream_t st);
@@ -314,5 +323,18 @@ template <typename T>
 hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hipStream_t st);
 
 hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStream_t st);
+
+// Class-packed layout (mgr_packed.hip): grid sizes in the internal 3-D form,
+// level count L and the start of every class segment off[0..L+1].
+constexpr int kMaxClassLevels = 64;
+struct PackArgs {
+    int64_t n[3];
+    int L;
+    int64_t off[kMaxClassLevels + 2];
+};
+// pack: in-place layout src -> class-packed dst; else the inverse.
+template <typename T>
+hipError_t launch_pack(const T* src, T* dst, const PackArgs& a, bool pack, hipStream_t st);
+
 
 }  // namespace mgr

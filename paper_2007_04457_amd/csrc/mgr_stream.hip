@@ -84,8 +84,7 @@ hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
 
 }  // namespace
 
-// Recomposition interpolation of one level step: a.A/av = coefficients
-// (level grid view), a.C/cv = output view, a.W/wv = corrected coarse values.
+// Coarse rows and columns of a streaming tile (for the batch's work items).
 void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2)
 {
     constexpr int Cf = cols_per_lane<float>(), Cd = cols_per_lane<double>();

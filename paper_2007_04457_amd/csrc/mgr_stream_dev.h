@@ -33,14 +33,12 @@ int resident_per_cu(K kern, int& cache)
 }
 
 // Geometry of the streaming level kernel, per problem dimensionality and
-// element size.  A lane owns CPL = 8 / sizeof(T) consecutive staged columns
-// (a column pair in FP32, one column in FP64), so that every global access of
-// a lane moves 8 bytes.
-//  3-D: a workgroup owns kT1 = 8 coarse rows x kT2 coarse columns (62 in
-//       FP32, 30 in FP64); its staged region is 19 fine rows x 2 kT2 + 3
-//       columns, one wave per row (rows r = wave, wave + 4, ...).
+// columns per lane CPL (cols_per_lane below: 1 for both element types).
+//  3-D: a workgroup owns kT1 = 8 coarse rows x kT2 = (64 CPL - 3) / 2 coarse
+//       columns (30 at CPL = 1); its staged region is 19 fine rows x
+//       2 kT2 + 3 columns, one wave per row (rows r = wave, wave + 4, ...).
 //  2-D (m0, 1, m2) and 1-D (1, 1, m2): one staged row, four waves side by
-//       side (kT2 = 254 in FP32, 126 in FP64).
+//       side (kT2 = (256 CPL - 3) / 2 = 126 at CPL = 1).
 template <bool kAct1, int CPL>
 struct LevelGeom {
     static constexpr int CW = kAct1 ? 1 : 4;            // waves per staged row
@@ -294,7 +292,8 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
         vF[q] = ok ? (unsigned)((kRowUni ? 0 : i1 * fs1) + (I2 + g2) * fs2) * S : kOut;
     }
 
-    // plane strides are below 2^31 (checked by the launcher): 32 x 32 -> 64 products
+    // plane strides are below 2^31 (a plane is under 2 GiB, checked when the
+    // arguments are validated): 32 x 32 -> 64 products
     const unsigned as0 = (unsigned)a.av.s[0], cs0 = (unsigned)a.cv.s[0], ws0 = (unsigned)a.wv.s[0],
                    fs0 = (unsigned)a.fv.s[0];
     auto mul64 = [](int i, unsigned st) { return (int64_t)((uint64_t)(unsigned)i * st); };

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2007_04457_amd as mgr
 from paper_2007_04457_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -75,6 +76,20 @@ def test_validation_errors_before_any_device_work(lib, fn):
     assert lib.mgr_last_error().decode() != ""
 
 
+def test_plane_addressing_limit(lib):
+    """Planes of 2 GiB or more are refused before any device work: the
+    kernels address within a plane with 32-bit byte offsets."""
+    assert _call(lib, "mgr_decompose", (2 ** 29 + 1,), dtype=0) == 2          # 1-D float32, 2 GiB + 4 B
+    assert _call(lib, "mgr_decompose", (3, 2 ** 28 + 1), dtype=1) == 2       # 2-D float64 row
+    assert _call(lib, "mgr_decompose_adjoint", (3, 16385, 16385), dtype=1) == 2
+    assert "2 GiB" in lib.mgr_last_error().decode()
+    assert _call(lib, "mgr_recompose", (3, 16385, 32769), dtype=0) == 2      # float32, 2 GiB + 192 KiB
+    # the largest accepted planes (validation passes; the call then needs a
+    # device, so on a machine without one it fails later with a HIP status)
+    assert _call(lib, "mgr_decompose", (2 ** 28 + 1,), dtype=0) not in (1, 2, 3, 4)
+    assert _call(lib, "mgr_decompose", (3, 8193, 8193), dtype=1) not in (1, 2, 3, 4)
+
+
 def test_status_strings(lib):
     for s in range(8):
         assert lib.mgr_status_string(s).decode()
@@ -85,3 +100,45 @@ def test_status_strings(lib):
 def test_bench_copy_validation(lib):
     assert lib.mgr_bench_copy(None, None, 16, None) == 1
     assert lib.mgr_bench_copy(16, 32, 15, None) == 1
+
+
+@pytest.mark.parametrize("shape,L", [((17, 9, 33), -1), ((9, 17), 1), ((33,), 0)])
+def test_class_masks_partition_the_grid(shape, L):
+    """class_masks: one mask per class 0..L, disjoint, covering every node,
+    each equal to the oracle's class map at that class."""
+    import oracle
+    masks = mgr.class_masks(shape, L)
+    full = oracle.max_levels(shape) if L < 0 else L
+    assert len(masks) == full + 1
+    cm = oracle.class_map(shape, L)
+    total = np.zeros(shape, dtype=int)
+    for l, m in enumerate(masks):
+        assert np.array_equal(m, cm == l), l
+        total += m
+    assert np.all(total == 1)
+
+
+@pytest.mark.parametrize("shape,L", [((17, 9, 33), -1), ((9, 17), 1), ((33,), 0), ((513, 513, 513), -1)])
+def test_class_offsets_match_oracle(shape, L):
+    if np.prod(shape) > 1e6:
+        full = oracle.max_levels(shape)
+        sizes = [int(np.prod([(n - 1) // 2 ** (full - l) + 1 for n in shape])) for l in range(full + 1)]
+        want = np.concatenate([[0], np.cumsum([sizes[0]] + [sizes[l] - sizes[l - 1] for l in range(1, full + 1)])])
+    else:
+        want = oracle.class_offsets(shape, L)
+    assert np.array_equal(mgr.class_offsets(shape, L), want)
+
+
+def test_packed_and_progressive_validation(lib):
+    """Argument errors of the class-packed and progressive entry points come
+    back before any device work."""
+    shp = _lib.shape_arg((9, 9))
+    assert lib.mgr_pack_classes(16, 16, 0, 2, shp, -1, None) == 1          # in place
+    assert lib.mgr_unpack_classes(16, 32, 0, 2, _lib.shape_arg((9, 10)), -1, None) == 2
+    assert lib.mgr_pack_classes(0, 32, 0, 2, shp, -1, None) == 1
+    assert lib.mgr_recompose_level(16, 32, 0, 2, shp, None, -1, 3, 0, None) == 3   # level > L
+    assert lib.mgr_recompose_level(16, 32, 0, 2, shp, None, -1, -1, 0, None) == 3
+    assert lib.mgr_recompose_level(16, 32, 0, 2, shp, None, -1, 1, 2, None) == 1   # bad layout flag
+    assert lib.mgr_recompose_level(16, 16, 0, 2, shp, None, -1, 1, 0, None) == 1   # in place
+    off = (ctypes.c_int64 * 4)()
+    assert lib.mgr_class_offsets(2, shp, -1, off) == 0 and list(off) == [0, 9, 25, 81]

@@ -123,3 +123,49 @@ def test_capture_before_streams_exist_is_refused():
         torch.cuda.synchronize()
         assert torch.equal(r, want), rep
     del g
+
+
+def test_capture_of_unprepared_decompose_is_refused():
+    """A decomposition of a problem that has no plan yet, called on a
+    capturing stream, fails with MGR_ERR_CAPTURE before anything is enqueued
+    (building the plan would allocate)."""
+    shape = (33, 9, 17)  # a shape no other test prepares
+    x = torch.from_numpy(synth.sinusoid_field(shape, 47)[0]).to(DEV)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    mgr.mgr_finalize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(mgr.MgrError) as ei:
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                mgr.mgr_decompose(x, y)
+    assert ei.value.status == 7
+    torch.cuda.synchronize()
+    del g
+    # the eager call afterwards builds the plan and runs
+    want = mgr.decompose(x)
+    torch.cuda.synchronize()
+    assert torch.isfinite(want).all()
+
+
+def test_workspace_cap_is_enforced(monkeypatch):
+    """MGR_WORKSPACE_MAX (bytes) caps the tables and workspace of a new
+    problem: a plan above it fails with MGR_ERR_ALLOC and nothing runs;
+    without the cap the same call succeeds."""
+    shape = (17, 33, 65)  # a shape no other test prepares
+    x = torch.from_numpy(synth.sinusoid_field(shape, 48)[0]).to(DEV)
+    torch.cuda.synchronize()
+    mgr.mgr_finalize()
+    monkeypatch.setenv("MGR_WORKSPACE_MAX", "4096")
+    with pytest.raises(mgr.MgrError) as ei:
+        mgr.decompose(x)
+    assert ei.value.status == 6
+    with pytest.raises(mgr.MgrError) as ei:
+        mgr.BatchPlan([shape], torch.float64)
+    assert ei.value.status == 6
+    monkeypatch.delenv("MGR_WORKSPACE_MAX")
+    y = mgr.decompose(x)
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
