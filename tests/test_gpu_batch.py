@@ -137,15 +137,18 @@ def test_batch_rejects_in_place_and_bad_shapes():
 
 
 def test_batch_graph_replay():
-    """The batch captured into a HIP graph: every replay, with eager work
-    and synchronisation between replays, matches the eager per-field
-    result."""
+    """The batch captured into a HIP graph: every replay, with eager calls of
+    the same plan on other tensors and synchronisation between replays,
+    writes the captured call's outputs from the captured call's inputs, and
+    the eager calls' outputs stay correct."""
     xs, coords = make_fields(MIXED[:5], torch.float32, 800)
+    others, _ = make_fields(MIXED[:5], torch.float32, 850)
     plan = mgr.BatchPlan([x.shape for x in xs], torch.float32, coords)
     dsts = [torch.empty_like(x) for x in xs]
     plan.decompose(xs, dsts)  # warm-up outside the capture
     torch.cuda.synchronize()
     want = [mgr.decompose(x, c) for x, c in zip(xs, coords)]
+    want_o = [mgr.decompose(x, c) for x, c in zip(others, coords)]
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -157,14 +160,39 @@ def test_batch_graph_replay():
     for rep in range(3):
         for d in dsts:
             d.fill_(float(rep + 7))
+        # an eager call of the same plan with other tensors before the replay
+        odst = [torch.full_like(x, -1.0) for x in others]
+        plan.decompose(others, odst)
         torch.cuda.synchronize()
+        for i in range(len(xs)):
+            assert torch.equal(odst[i], want_o[i]), ("eager", rep, i)
+            assert torch.equal(dsts[i], torch.full_like(dsts[i], float(rep + 7))), ("untouched", rep, i)
         g.replay()
-        torch.cuda.synchronize()
         torch.cuda.synchronize()
         for i in range(len(xs)):
             assert torch.equal(dsts[i], want[i]), (rep, i)
-        _ = [mgr.decompose(x, c) for x, c in zip(xs, coords)]  # eager work between replays
+            assert torch.equal(odst[i], want_o[i]), ("eager after replay", rep, i)
+        _ = [mgr.decompose(x, c) for x, c in zip(xs, coords)]  # per-field work between replays
     del g
+    plan.close()
+
+
+def test_batch_plan_survives_finalize():
+    """A batch plan owns its tables: mgr_finalize (which frees the per-field
+    cache) leaves it working, with the same results as before."""
+    xs, coords = make_fields(MIXED[:4], torch.float64, 870)
+    plan = mgr.BatchPlan([x.shape for x in xs], torch.float64, coords)
+    before = plan.decompose(xs)
+    torch.cuda.synchronize()
+    mgr.mgr_finalize()
+    after = plan.decompose(xs)
+    plan.set_config(4)
+    again = plan.decompose(xs)
+    torch.cuda.synchronize()
+    for i in range(len(xs)):
+        assert torch.equal(before[i], after[i]), i
+        assert torch.equal(before[i], again[i]), i
+        assert torch.equal(before[i], mgr.decompose(xs[i], coords[i])), i
     plan.close()
 
 
@@ -179,4 +207,17 @@ def test_batch_full_workload_96_fields():
     torch.cuda.synchronize()
     for i, x in enumerate(xs):
         assert torch.equal(ys[i], mgr.decompose(x)), (i, shapes[i])
+    # a sample against the FP64 oracle: the largest 2-D and 3-D fields, the
+    # smallest field, and a few more picked by a fixed draw
+    sizes = [int(np.prod(s)) for s in shapes]
+    big2 = max(range(80, len(shapes)), key=lambda i: sizes[i])
+    big3 = max(range(80), key=lambda i: sizes[i])
+    small = min(range(len(shapes)), key=lambda i: sizes[i])
+    extra = np.random.default_rng(96).choice(len(shapes), 3, replace=False)
+    for i in sorted({big2, big3, small, *[int(e) for e in extra]}):
+        print(f"[batch] field {i} {shapes[i]} vs oracle", flush=True)
+        xd = xs[i].double().cpu().numpy()
+        ref = oracle.decompose(xd)
+        err = float(np.max(np.abs(ys[i].double().cpu().numpy() - ref))) / float(np.max(np.abs(xd)))
+        assert err <= TOL[torch.float32], (i, shapes[i], err)
     plan.close()
