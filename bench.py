@@ -27,22 +27,18 @@ HBM_PEAK_GBPS = 8000.0
 SHAPE = (513, 513, 513)
 SEED_SIN, SEED_BLOB = 1, 2
 
-# Dominant kernel and its algorithmic bytes per level-0 launch.  The streaming
-# decomposition kernel reads the level grid once (V nodes) and writes every
-# node once (coefficients at fine-only nodes, u at coarse positions so rows
-# are written whole), the packed coarse values (Vc) and the load vector (Vc).
+# Dominant kernel and its algorithmic bytes per level-0 launch: the method's
+# floor for one level step, reading the level grid once and writing every
+# node once, 2 V s.  This design's intermediates (the packed coarse values
+# and the load vector, Vc each) are not part of the floor: they show up in
+# the measured traffic instead.
 DOMINANT = "stream_dec"
 
 
 def algorithmic_bytes(kernel, shape, s):
     V = int(np.prod(shape))
-    Vc = int(np.prod([(n + 1) // 2 for n in shape]))
-    if kernel == "stream_dec":
-        return (2 * V + 2 * Vc) * s
-    if kernel == "stream_load":
-        return (V + Vc) * s
-    if kernel == "interp_recompose":
-        return (V + Vc + V) * s  # coefficients + coarse values in, V out
+    if kernel in ("stream_dec", "interp_recompose", "adjoint"):
+        return 2 * V * s
     raise ValueError(kernel)
 
 
@@ -180,36 +176,118 @@ def adjoint_timing(mgr, torch, synth, oracle_free=True):
             "fwd_bwd_over_decompose": round(t_fb / t_dec, 3)}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_threads():
+    """Threads the all-core leg uses: the cores this process may run on,
+    capped by OMP_NUM_THREADS when it is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def cpu_baseline(u_sin):
-    """The CPU oracle (plain C, FP64, one thread) on one step of the headline
-    workload: the 513^3 sinusoid-plus-noise field (rounded to float32, as the
-    GPU sees it) decomposed and recomposed once.  Rate in the metric's unit:
+    """The CPU oracle (plain C, FP64) on one step of the headline workload:
+    the 513^3 sinusoid-plus-noise field (rounded to float32, as the GPU sees
+    it) decomposed and recomposed once, on all the host cores this process
+    may use (OpenMP over independent fibres and nodes; bitwise the same
+    output as one thread) and on one thread.  Rate in the metric's unit:
     float32 input bytes (4 per node) per direction, as for the GPU."""
     import oracle
 
     u = u_sin.astype(np.float32).astype(np.float64)
-    t0 = time.perf_counter()
-    d = oracle.decompose(u)
-    oracle.recompose(d)
-    t = time.perf_counter() - t0
     n = u.size
-    return {"value": round(2 * n * 4 / t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+    legs = {}
+    for threads in (cpu_threads(), 1):
+        prev = oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        d = oracle.decompose(u)
+        oracle.recompose(d)
+        legs[threads] = time.perf_counter() - t0
+        oracle.set_threads(prev)
+        del d
+    nt = cpu_threads()
+    t_all, t_one = legs[nt], legs[1]
+    return {"value": round(2 * n * 4 / t_all / 1e9, 4), "unit": "GB/s", "cores": nt, "kind": "oracle",
             "sample": f"one decompose+recompose of the full 513^3 sinusoid field (FP64 oracle, "
-                      f"single thread, {t:.1f} s); GB/s counted as float32 input bytes per direction"}
+                      f"{nt} threads, {t_all:.1f} s; one thread {t_one:.1f} s); GB/s counted as float32 "
+                      f"input bytes per direction",
+            "single_thread_value": round(2 * n * 4 / t_one / 1e9, 4),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+# The other plain-method workloads (parity cases in the tests), timed for
+# their throughput: (name, shape, dtype, generator, seed, nonuniform).
+OTHER_WORKLOADS = [
+    ("65^3_f64_sinusoid", (65, 65, 65), "f64", "sinusoid", 0, False),
+    ("8193^2_f64_nonuniform", (8193, 8193), "f64", "sinusoid", 3, True),
+    ("1025x1025x257_f32_nonuniform", (1025, 1025, 257), "f32", "sinusoid", 4, True),
+]
+
+
+def other_workloads(mgr, torch, synth, steps, warmup):
+    out = {}
+    for name, shape, dtn, gen, seed, nu in OTHER_WORKLOADS:
+        print(f"[bench] {name}: {warmup} warmup + {steps} steps", file=sys.stderr, flush=True)
+        dt = torch.float32 if dtn == "f32" else torch.float64
+        s = 4 if dtn == "f32" else 8
+        u, coords = getattr(synth, gen + "_field")(shape, seed, nonuniform=nu)
+        x = torch.from_numpy(u).to(dt).cuda()
+        del u
+        y, r = torch.empty_like(x), torch.empty_like(x)
+        mgr.mgr_prepare(dt, shape, coords)
+
+        def dec():
+            mgr.mgr_decompose(x, y, coords)
+
+        def rec():
+            mgr.mgr_recompose(y, r, coords)
+
+        for _ in range(warmup):
+            dec()
+            rec()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dec()
+            rec()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        td = event_ms(torch, dec)
+        tr = event_ms(torch, rec)
+        err = float((r - x).abs().max().item() / x.abs().max().item())
+        n = x.numel()
+        out[name] = {"GBps": round(2 * n * s / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 4),
+                     "t_decompose_ms": round(td, 4), "t_recompose_ms": round(tr, 4),
+                     "roundtrip_max_rel_err": err}
+        del x, y, r
+        torch.cuda.empty_cache()
+    return out
 
 
 # HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by the same counters on a copy kernel of known size; valid
 # only while the kernel source matches the one the counters were taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_dec_513cube_f32_counters.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_dec_513cube_{}_counters.md")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2007_04457_amd", "csrc", f) for f in (
     "mgr_internal.h", "mgr_stream_dev.h", "mgr_stream.hip")]
 
 
-def measured_traffic():
+def measured_traffic(dt_name):
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(TRAFFIC_FILE.format(dt_name)).read()
         h = hashlib.sha256()
         for f in KERNEL_SRCS:
             h.update(open(f, "rb").read())
@@ -265,7 +343,7 @@ def main():
     u_blob = None if args.quick else synth.blob_field(SHAPE, SEED_BLOB)[0]
 
     results = {}
-    roof = None
+    roofs = {}
     for dt_name, dt in (("f32", torch.float32), ("f64", torch.float64)):
         if args.quick and dt_name == "f64":
             continue
@@ -277,7 +355,8 @@ def main():
             y = torch.empty_like(x)
             r = torch.empty_like(x)
             mgr.mgr_prepare(dt, SHAPE)
-            headline = (dt_name == "f32" and fname == "sinusoid")
+            # the dominant kernel is timed in the sinusoid runs of both dtypes
+            headline = (fname == "sinusoid")
             print(f"[bench] {dt_name} {fname}: {args.warmup} warmup + {args.steps} steps",
                   file=sys.stderr, flush=True)
             def start_timing():
@@ -293,11 +372,11 @@ def main():
                 per_launch_ms = ms_tot / launches
                 ab = algorithmic_bytes(DOMINANT, SHAPE, s)
                 achieved = ab / (per_launch_ms * 1e-3) / 1e9
-                roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                        "traffic": measured_traffic(),
-                        "kernel": DOMINANT, "level": 0, "launch_ms": round(per_launch_ms, 4),
-                        "launches": launches, "algorithmic_bytes": ab}
+                roofs[dt_name] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                                  "traffic": measured_traffic(dt_name),
+                                  "kernel": DOMINANT, "level": 0, "launch_ms": round(per_launch_ms, 4),
+                                  "launches": launches, "algorithmic_bytes": ab}
             td, tr = split_times(mgr, torch, x, y, r)
             torch.cuda.synchronize()
             err = float((r - x).abs().max().item() / x.abs().max().item())
@@ -312,6 +391,7 @@ def main():
     copy_gbps = copy_bandwidth(mgr, torch)
     extra = {}
     if not args.quick:
+        extra["other_workloads"] = other_workloads(mgr, torch, synth, max(3, args.steps // 2), args.warmup)
         print("[bench] batched 96 fields vs serial", file=sys.stderr, flush=True)
         extra["batched"] = batched_vs_serial(mgr, torch, synth)
         print("[bench] adjoint / autograd at 257^3", file=sys.stderr, flush=True)
@@ -324,7 +404,8 @@ def main():
         "config": {"workload": "513^3 uniform grid, sinusoid-plus-noise field (seed 1), "
                                f"full decomposition ({L} level steps) then recomposition",
                    "shape": list(SHAPE), "nlevels": L},
-        "roofline": roof,
+        "roofline": roofs.get("f32"),
+        "roofline_f64": roofs.get("f64"),
         "t_decompose_ms": head["t_decompose_ms"], "t_recompose_ms": head["t_recompose_ms"],
         "roundtrip_max_rel_err": head["roundtrip_max_rel_err"],
         "copy_kernel_GBps": round(copy_gbps, 1),
