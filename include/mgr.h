@@ -99,6 +99,16 @@ int mgr_decompose_adjoint(const void* src, void* dst, int dtype, int ndim,
                           const int64_t* shape, const double* const* coords,
                           int nlevels, void* stream);
 
+/* Adjoint (transpose) of mgr_recompose, i.e. the inverse transpose D^{-T} of
+ * the decomposition, under the same inner product: dst = D^{-T} src.
+ * Derived from Eq. (1)-(2); not in the paper.  Per level step, fine to
+ * coarse: g_c' = g_c + Pi^T g_f (transposed interpolation), y = M_{l-1}^{-1}
+ * g_c' (tridiagonal solves), out_f = g_f - (M P) y at the fine-only nodes;
+ * the coarsest g_c' are the class-0 outputs.  dst == src is allowed. */
+int mgr_recompose_adjoint(const void* src, void* dst, int dtype, int ndim,
+                          const int64_t* shape, const double* const* coords,
+                          int nlevels, void* stream);
+
 /* Builds and uploads the tables and allocates the workspace of a problem
  * (synchronously), and creates the recomposition's streams of the current
  * device, so that later calls on a capturing stream allocate and create

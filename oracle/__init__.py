@@ -33,7 +33,8 @@ def _load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         dp = ctypes.POINTER(ctypes.c_double)
         dpp = ctypes.POINTER(dp)
-        for name in ("oracle_decompose", "oracle_recompose", "oracle_decompose_adjoint"):
+        for name in ("oracle_decompose", "oracle_recompose", "oracle_decompose_adjoint",
+                     "oracle_recompose_adjoint"):
             fn = getattr(lib, name)
             fn.argtypes = [dp, ctypes.c_int, i64p, dpp, ctypes.c_int]
             fn.restype = ctypes.c_int
@@ -118,6 +119,11 @@ def recompose(u, coords=None, nlevels=-1):
 def decompose_adjoint(g, coords=None, nlevels=-1):
     """Transpose of decompose under the Euclidean inner product."""
     return _run("oracle_decompose_adjoint", g, coords, nlevels)
+
+
+def recompose_adjoint(g, coords=None, nlevels=-1):
+    """Transpose of recompose (the inverse transpose of decompose)."""
+    return _run("oracle_recompose_adjoint", g, coords, nlevels)
 
 
 def coefficients_level(u, k, coords=None):

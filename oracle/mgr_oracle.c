@@ -586,6 +586,93 @@ int oracle_decompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
     return rc;
 }
 
+/* Transpose of the recomposition, i.e. the inverse transpose D^{-T} of the
+ * decomposition (derived from Eq. (1)-(2); not in the paper).  Recomposition
+ * step k maps (y_c, y_f) to x_c = y_c - A y_f, x_f = y_f + Phi x_c (A as for
+ * the decomposition's transpose above), so its transpose maps (g_c, g_f) to
+ *     g_c' = g_c + Phi^T g_f,
+ *     g_f' = g_f - A^T g_c' = g_f - E_f^T M P M_c^{-1} g_c'.
+ * Recomposition runs coarse to fine, so its transpose runs fine to coarse. */
+int oracle_recompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
+                             const double* const* coords, int nlevels)
+{
+    grid_t g;
+    if (!g_arr) return 1;
+    int rc = setup(&g, ndim, shape, coords, &nlevels);
+    if (rc) return rc;
+    int nd = g.nd;
+    for (int k = 0; k < nlevels && rc == 0; k++) {
+        int64_t m[MAXD], mc[MAXD], V = 1, j[MAXD] = {0, 0, 0, 0};
+        double* y[MAXD] = {0};
+        for (int d = 0; d < nd; d++) {
+            m[d] = lsize(&g, d, k);
+            mc[d] = lsize(&g, d, k + 1);
+            V *= m[d];
+            y[d] = level_coords(&g, d, k);
+            if (!y[d]) rc = 6;
+        }
+        double* a = (double*)malloc(sizeof(double) * (size_t)V);
+        double* b = (double*)malloc(sizeof(double) * (size_t)V);
+        if (!a || !b) rc = 6;
+        if (rc == 0) {
+            /* g_c' = g_c + Phi^T g_f: each fine-only value goes to its coarse
+             * corners with the interpolation weights. */
+            do {
+                int odd[MAXD], t = 0;
+                for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
+                if (t == 0) continue;
+                double vf = g_arr[offset_of(&g, j, k)];
+                for (int mask = 0; mask < (1 << nd); mask++) {
+                    int skip = 0;
+                    double w = 1.0;
+                    int64_t q[MAXD];
+                    for (int d = 0; d < nd; d++) {
+                        int up = (mask >> d) & 1;
+                        if (!odd[d]) {
+                            if (up) { skip = 1; break; }
+                            q[d] = j[d];
+                        } else {
+                            double aa = interp_a(y[d], j[d]);
+                            q[d] = up ? j[d] + 1 : j[d] - 1;
+                            w *= up ? aa : (1.0 - aa);
+                        }
+                    }
+                    if (skip) continue;
+                    g_arr[offset_of(&g, q, k)] += w * vf;
+                }
+            } while (next_index(nd, j, m));
+            /* w = M_c^{-1} g_c' */
+            int64_t idx = 0;
+            memset(j, 0, sizeof(j));
+            do { a[idx++] = g_arr[offset_of(&g, j, k + 1)]; } while (next_index(nd, j, mc));
+            rc = stage_correction(a, &g, k, 1);
+            /* t = (M P) w along every dimension (first to last) */
+            int64_t sh[MAXD];
+            for (int d = 0; d < nd; d++) sh[d] = mc[d];
+            for (int d = 0; d < nd && rc == 0; d++) {
+                rc = along_dim(a, b, nd, sh, d, OP_PROLONG_MASS, y[d]);
+                sh[d] = 2 * sh[d] - 1;
+                double* tt = a; a = b; b = tt;
+            }
+            /* g_f' = g_f - t at the fine-only nodes */
+            if (rc == 0) {
+                memset(j, 0, sizeof(j));
+                idx = 0;
+                do {
+                    int fine = 0;
+                    for (int d = 0; d < nd; d++) if (j[d] & 1) fine = 1;
+                    if (fine) g_arr[offset_of(&g, j, k)] -= a[idx];
+                    idx++;
+                } while (next_index(nd, j, m));
+            }
+        }
+        free(a);
+        free(b);
+        for (int d = 0; d < nd; d++) free(y[d]);
+    }
+    return rc;
+}
+
 int oracle_coefficients_level(double* u, int ndim, const int64_t* shape,
                               const double* const* coords, int k)
 {

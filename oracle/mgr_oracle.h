@@ -45,6 +45,11 @@ int oracle_recompose(double* u, int ndim, const int64_t* shape,
 int oracle_decompose_adjoint(double* g, int ndim, const int64_t* shape,
                              const double* const* coords, int nlevels);
 
+/* Transpose of the recomposition (= inverse transpose of the
+ * decomposition) under the same inner product; fine to coarse. */
+int oracle_recompose_adjoint(double* g, int ndim, const int64_t* shape,
+                             const double* const* coords, int nlevels);
+
 /* Per-stage entry points for one level step k (stride 2^k), Sec. II-A.
  * coefficients: step "compute coefficients" only, in place on u.
  * load_vector : f = R M vec(C) for the level step k, written packed to f

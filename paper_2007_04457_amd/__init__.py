@@ -19,10 +19,12 @@ from ._lib import MgrError, MGR_F32, MGR_F64
 
 __all__ = [
     "MgrError", "MGR_F32", "MGR_F64",
-    "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_prepare",
+    "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_recompose_adjoint",
+    "mgr_prepare",
     "mgr_class_map", "class_masks", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
-    "decompose", "recompose", "decompose_adjoint", "Decompose", "kernel_classes", "BatchPlan",
+    "decompose", "recompose", "decompose_adjoint", "recompose_adjoint", "Decompose", "Recompose",
+    "kernel_classes", "BatchPlan",
     "class_offsets", "pack_classes", "unpack_classes", "recompose_level",
 ]
 
@@ -78,6 +80,11 @@ def mgr_recompose(src, dst, coords=None, nlevels=-1):
 def mgr_decompose_adjoint(src, dst, coords=None, nlevels=-1):
     """dst <- D^T src, the transpose of the decomposition."""
     return _call("mgr_decompose_adjoint", src, dst, coords, nlevels)
+
+
+def mgr_recompose_adjoint(src, dst, coords=None, nlevels=-1):
+    """dst <- R^T src = D^{-T} src, the transpose of the recomposition."""
+    return _call("mgr_recompose_adjoint", src, dst, coords, nlevels)
 
 
 def mgr_prepare(dtype, shape, coords=None, nlevels=-1):
@@ -266,6 +273,12 @@ def decompose_adjoint(g, coords=None, nlevels=-1, out=None):
     return mgr_decompose_adjoint(g, out, coords, nlevels)
 
 
+def recompose_adjoint(g, coords=None, nlevels=-1, out=None):
+    if out is None:
+        out = _torch().empty_like(g)
+    return mgr_recompose_adjoint(g, out, coords, nlevels)
+
+
 def _make_autograd():
     torch = _torch()
 
@@ -283,19 +296,37 @@ def _make_autograd():
         def backward(ctx, g):
             return decompose_adjoint(g.contiguous(), ctx.coords, ctx.nlevels), None, None
 
-    return Decompose
+    class Recompose(torch.autograd.Function):
+        """x = D^{-1} y with the recomposition's hand-written adjoint as
+        backward: dL/dy = D^{-T} dL/dx."""
+
+        @staticmethod
+        def forward(ctx, y, coords=None, nlevels=-1):
+            ctx.coords = coords
+            ctx.nlevels = nlevels
+            return recompose(y.contiguous(), coords, nlevels)
+
+        @staticmethod
+        def backward(ctx, g):
+            return recompose_adjoint(g.contiguous(), ctx.coords, ctx.nlevels), None, None
+
+    return {"Decompose": Decompose, "Recompose": Recompose}
 
 
-class _LazyDecompose:
-    _cls = None
+class _LazyFunction:
+    _classes = None
 
-    def __getattr__(self, name):
-        if _LazyDecompose._cls is None:
-            _LazyDecompose._cls = _make_autograd()
-        return getattr(_LazyDecompose._cls, name)
+    def __init__(self, name):
+        self._name = name
+
+    def __getattr__(self, attr):
+        if _LazyFunction._classes is None:
+            _LazyFunction._classes = _make_autograd()
+        return getattr(_LazyFunction._classes[self._name], attr)
 
 
-Decompose = _LazyDecompose()
+Decompose = _LazyFunction("Decompose")
+Recompose = _LazyFunction("Recompose")
 
 
 class BatchPlan:

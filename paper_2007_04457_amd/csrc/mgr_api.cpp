@@ -47,6 +47,7 @@ constexpr int kMaxDim = 3;
 struct LevelLayout {
     int64_t m[3], mc[3];
     size_t w[3], K[3], lf[3], ip[3];  // lf, ip: plain Thomas factors of M_{l-1}
+    size_t PT[3];  // P^T as a 5-point row per coarse node (transposed interpolation)
     size_t sup[3];  // plain super-diagonal of M_{l-1}
     size_t L[3], U[3], IP[3], A[3], B[3], ssub[3], ssup[3], sl[3], sip[3], su[3];
     int S[3];
@@ -182,7 +183,7 @@ std::vector<double> axis_positions(int64_t n, const double* x)
 }
 
 struct DimTab {
-    std::vector<double> w, K;
+    std::vector<double> w, K, PT;
 };
 
 // Tables of one dimension at level step k from the level-grid positions y.
@@ -223,6 +224,12 @@ DimTab build_dim(const std::vector<double>& y)
             t.K[(size_t)(5 * i + tt + 2)] = s;
         }
     }
+    // P^T alone in the same 5-point form: coarse node i collects fine 2i - 1,
+    // 2i and 2i + 1 (the recomposition adjoint's transposed interpolation)
+    t.PT.assign((size_t)(5 * mc), 0.0);
+    for (int64_t i = 0; i < mc; i++)
+        for (int64_t j = 2 * i - 1; j <= 2 * i + 1; j++)
+            if (j >= 0 && j < m) t.PT[(size_t)(5 * i + (j - 2 * i) + 2)] = PT(i, j);
     return t;
 }
 
@@ -380,7 +387,7 @@ void plan_layout(Plan& p, const double* const* coords, bool dec_only, std::vecto
         for (int d = 0; d < 3; d++) {
             ly.m[d] = p.active[d] ? ((p.n[d] - 1) >> k) + 1 : 1;
             ly.mc[d] = p.active[d] ? (ly.m[d] + 1) / 2 : 1;
-            ly.w[d] = ly.K[d] = ly.lf[d] = ly.ip[d] = 0;
+            ly.w[d] = ly.K[d] = ly.lf[d] = ly.ip[d] = ly.PT[d] = 0;
             ly.sup[d] = ly.L[d] = ly.U[d] = ly.IP[d] = ly.A[d] = ly.B[d] = 0;
             ly.ssub[d] = ly.ssup[d] = ly.sl[d] = ly.sip[d] = ly.su[d] = 0;
             ly.S[d] = 1;
@@ -390,6 +397,7 @@ void plan_layout(Plan& p, const double* const* coords, bool dec_only, std::vecto
             DimTab t = build_dim(y);
             push_table(host, t.w, &ly.w[d]);
             push_table(host, t.K, &ly.K[d]);
+            if (!dec_only) push_table(host, t.PT, &ly.PT[d]);
             std::vector<double> yc((size_t)ly.mc[d]);
             for (int64_t i = 0; i < ly.mc[d]; i++) yc[(size_t)i] = y[(size_t)(2 * i)];
             SolveTab sv = build_solve(yc);
@@ -597,6 +605,16 @@ DimTables<T> tables_of(const Plan& p, int k)
         tb.w[d] = a ? base + ly.w[d] : nullptr;
         tb.K[d] = a ? base + ly.K[d] : nullptr;
     }
+    return tb;
+}
+
+// Interpolation weights with P^T in place of the load-vector stencil.
+template <typename T>
+DimTables<T> pt_tables_of(const Plan& p, int k)
+{
+    DimTables<T> tb = tables_of<T>(p, k);
+    const T* base = (const T*)p.tables;
+    for (int d = 0; d < 3; d++) tb.K[d] = p.active[d] ? base + p.lv[(size_t)k].PT[d] : nullptr;
     return tb;
 }
 
@@ -994,7 +1012,75 @@ int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     return MGR_OK;
 }
 
-enum Direction { DIR_DEC, DIR_REC, DIR_ADJ };
+// Transpose of the recomposition (D^{-T}), fine to coarse.  Per level step,
+// with g the level grid (the input at k = 0, else W_k):
+//   Ft = P^T g_f (load-vector pass with P^T as its stencil; coarse positions
+//        read as zero),
+//   G = g_c + Ft -> W_{k+1} (the next step's grid), and -G into the solve
+//        buffer,
+//   y = M_c^{-1} (-G) (solves, dimensions first to last),
+//   out_f = g_f + (M P) y at the level grid's fine-only nodes, written to their
+//        final places in dst (the adjoint kernel; the values it also writes at
+//        coarse positions are overwritten by the coarser steps),
+// and finally the coarsest grid W_L to its nodes.  In place is safe: each
+// step reads the input's coarse values (into W_{k+1}) before the expansion
+// overwrites them, and a fine output depends on the input at its own node
+// only.
+template <typename T>
+int run_recompose_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
+{
+    const int L = p.nlevels;
+    if (L == 0) return identity_copy<T>(p, src_, dst_, st);
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    T* ws = (T*)p.ws;
+    for (int k = 0; k < L; k++) {
+        const LevelLayout& ly = p.lv[(size_t)k];
+        const T* g = (k == 0) ? src : ws + p.Woff[(size_t)k];
+        const View3 gv = (k == 0) ? full_view(p) : packed(ly.m);
+        T* F = corr<T>(p, k);
+        const View3 cv = packed(ly.mc);
+        {
+            StreamArgs<T> a;
+            a.A = g;
+            a.Z = nullptr;
+            a.av = gv;
+            a.C = nullptr;
+            a.cv = gv;
+            a.W = nullptr;
+            a.wv = cv;
+            a.F = F;
+            a.fv = cv;
+            a.tb = pt_tables_of<T>(p, k);
+            a.write_coarse = 0;
+            a.chunk = a.nt1 = a.nt2 = a.nch = 0;
+            MGR_TRY(timed(KC_STREAM_LOAD, k, st, [&] { return launch_stream_level<T>(a, false, st); }),
+                    "transposed interpolation launch");
+        }
+        View3 gc = gv;  // the coarse nodes of the level grid
+        for (int d = 0; d < 3; d++) {
+            gc.n[d] = ly.mc[d];
+            gc.s[d] = p.active[d] ? 2 * gv.s[d] : gv.s[d];
+        }
+        T* W = ws + p.Woff[(size_t)k + 1];
+        MGR_TRY(launch_add_split<T>(g, gc, F, W, F, st), "combine launch");
+        int rc = solve_all<T>(p, k, true, F, st);
+        if (rc) return rc;
+        MGR_TRY(timed(KC_ADJOINT, k, st,
+                      [&] {
+                          return launch_stream_adjoint<T>(g, gv, F, W, cv, dst, level_view(p, k), tables_of<T>(p, k),
+                                                          st);
+                      }),
+                "recomposition adjoint level launch");
+    }
+    View3 cl = level_view(p, L);
+    MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                  [&] { return launch_copy_view<T>(ws + p.Woff[(size_t)L], nullptr, packed(cl.n), dst, cl, st); }),
+            "coarsest scatter");
+    return MGR_OK;
+}
+
+enum Direction { DIR_DEC, DIR_REC, DIR_ADJ, DIR_RADJ };
 
 int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
         const double* const* coords, int nlevels, void* stream)
@@ -1009,12 +1095,14 @@ int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const in
         switch (dir) {
             case DIR_DEC: return run_decompose<float>(*p, src, dst, st);
             case DIR_REC: return run_recompose<float>(*p, src, dst, st);
+            case DIR_RADJ: return run_recompose_adjoint<float>(*p, src, dst, st);
             default: return run_adjoint<float>(*p, src, dst, st);
         }
     }
     switch (dir) {
         case DIR_DEC: return run_decompose<double>(*p, src, dst, st);
         case DIR_REC: return run_recompose<double>(*p, src, dst, st);
+        case DIR_RADJ: return run_recompose_adjoint<double>(*p, src, dst, st);
         default: return run_adjoint<double>(*p, src, dst, st);
     }
 }
@@ -1527,6 +1615,18 @@ int mgr_decompose_adjoint(const void* src, void* dst, int dtype, int ndim, const
 {
     try {
         return run(DIR_ADJ, src, dst, dtype, ndim, shape, coords, nlevels, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_recompose_adjoint(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                          const double* const* coords, int nlevels, void* stream)
+{
+    try {
+        return run(DIR_RADJ, src, dst, dtype, ndim, shape, coords, nlevels, stream);
     } catch (const std::bad_alloc&) {
         return fail(MGR_ERR_ALLOC, "host allocation failed");
     } catch (...) {

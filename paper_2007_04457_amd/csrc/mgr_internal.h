@@ -323,6 +323,10 @@ template <typename T>
 hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hipStream_t st);
 
 hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStream_t st);
+// Y[i] = X(view xv)[i] + Z[i] and N[i] = -Y[i] for every node i of xv, with
+// Z, Y, N packed (N may alias Z).
+template <typename T>
+hipError_t launch_add_split(const T* X, View3 xv, const T* Z, T* Y, T* N, hipStream_t st);
 
 // Class-packed layout (mgr_packed.hip): grid sizes in the internal 3-D form,
 // level count L and the start of every class segment off[0..L+1].

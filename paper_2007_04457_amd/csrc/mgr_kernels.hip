@@ -127,6 +127,20 @@ k_copy_view(const T* __restrict__ X, const T* __restrict__ Z, View3 xv, T* __res
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_add_split(const T* __restrict__ X, View3 xv, const T* Z, T* __restrict__ Y, T* N, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        int64_t j[3];
+        decode3(idx, xv.n, j);
+        const T v = X[at(xv, j[0], j[1], j[2])] + Z[idx];
+        Y[idx] = v;
+        N[idx] = -v;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_bench_copy(const uint4* __restrict__ s, uint4* __restrict__ d, int64_t n16)
 {
@@ -158,6 +172,14 @@ hipError_t launch_copy_view(const T* X, const T* Z, View3 xv, T* Y, View3 yv, hi
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_add_split(const T* X, View3 xv, const T* Z, T* Y, T* N, hipStream_t st)
+{
+    const int64_t total = vol(xv);
+    hipLaunchKernelGGL(k_add_split<T>, dim3(grid_for(total)), dim3(kBlock), 0, st, X, xv, Z, Y, N, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStream_t st)
 {
     int64_t n16 = (int64_t)(nbytes / 16);
@@ -169,7 +191,8 @@ hipError_t launch_bench_copy(const void* src, void* dst, size_t nbytes, hipStrea
 #define MGR_INSTANTIATE(T)                                                                      \
     template hipError_t launch_coef_decompose<T>(const T*, View3, T*, View3, T*, View3,         \
                                                  DimTables<T>, hipStream_t);                    \
-    template hipError_t launch_copy_view<T>(const T*, const T*, View3, T*, View3, hipStream_t);
+    template hipError_t launch_copy_view<T>(const T*, const T*, View3, T*, View3, hipStream_t);      \
+    template hipError_t launch_add_split<T>(const T*, View3, const T*, T*, T*, hipStream_t);
 
 MGR_INSTANTIATE(float)
 MGR_INSTANTIATE(double)

@@ -116,12 +116,23 @@ def test_adjoint_matches_oracle(case):
     assert err <= TOL[dt], err
 
 
+@pytest.mark.parametrize("case", CASES, ids=[case_id(c) for c in CASES])
+def test_recompose_adjoint_matches_oracle(case):
+    shape, dt, nu, L = case
+    g, gd, coords = field(shape, 400 + len(shape), nu, dt)
+    want = oracle.recompose_adjoint(gd, coords, L)
+    a = mgr.recompose_adjoint(g.to(DEV), coords, L)
+    torch.cuda.synchronize()
+    err = rel_err(a.double().cpu().numpy(), want, np.max(np.abs(gd)))
+    assert err <= TOL[dt], err
+
+
 @pytest.mark.parametrize("shape,dt", [((65, 33, 17), torch.float64), ((129, 65), torch.float32),
                                       ((257,), torch.float64)])
 def test_in_place_equals_out_of_place(shape, dt, tail_mode):
     x, _, coords = field(shape, 7, True, dt)
     xg = x.to(DEV)
-    for fn in (mgr.mgr_decompose, mgr.mgr_recompose, mgr.mgr_decompose_adjoint):
+    for fn in (mgr.mgr_decompose, mgr.mgr_recompose, mgr.mgr_decompose_adjoint, mgr.mgr_recompose_adjoint):
         out = torch.empty_like(xg)
         fn(xg, out, coords)
         inp = xg.clone()
@@ -171,6 +182,26 @@ def test_autograd_function():
     want = oracle.decompose_adjoint(2.0 * np.power(2.0, oracle.class_map(shape)) * d, coords)
     err = rel_err(xg.grad.cpu().numpy(), want, np.max(np.abs(want)))
     assert err <= 1e-12, err
+
+
+def test_autograd_through_recompose():
+    """x = R y with R the recomposition; the gradient of sum(w * x^2) with
+    respect to y is R^T (2 w x), through the recomposition's adjoint."""
+    shape = (17, 9, 33)
+    y0, yd, coords = field(shape, 13, True, torch.float64)
+    yg = y0.to(DEV).requires_grad_(True)
+    x = mgr.Recompose.apply(yg, coords, -1)
+    w = torch.from_numpy(np.linspace(0.5, 2.0, int(np.prod(shape))).reshape(shape)).to(DEV)
+    (w * x * x).sum().backward()
+    xr = oracle.recompose(yd, coords)
+    want = oracle.recompose_adjoint(2.0 * w.cpu().numpy() * xr, coords)
+    err = rel_err(yg.grad.cpu().numpy(), want, np.max(np.abs(want)))
+    assert err <= 1e-12, err
+    # decompose then recompose is the identity, and so is its gradient
+    xg = torch.from_numpy(yd).to(DEV).requires_grad_(True)
+    out = mgr.Recompose.apply(mgr.Decompose.apply(xg, coords, -1), coords, -1)
+    (w * out).sum().backward()
+    assert float((xg.grad - w).abs().max()) <= 1e-12 * float(w.abs().max())
 
 
 def test_prepare_and_repeat_calls_are_deterministic():

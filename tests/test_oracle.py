@@ -399,3 +399,33 @@ def test_recompose_level_is_the_projection(shape, nonuniform):
         assert got.shape == want.shape
         assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(u)), l
     assert np.max(np.abs(oracle.recompose_level(y, L, coords, L) - u)) <= 1e-13 * np.max(np.abs(u))
+
+
+
+def test_recompose_adjoint_equals_dense_inverse_transpose():
+    """The recomposition's transpose equals (D^-1)^T, with D the dense
+    decomposition matrix built from the L2 projections."""
+    rng = np.random.default_rng(41)
+    for shape, nonuni in [((9, 9, 9), False), ((9, 5, 9), True), ((17, 9), True), ((33,), True)]:
+        coords = rand_coords(rng, shape) if nonuni else None
+        L = oracle.max_levels(shape)
+        D = dense_ref.decompose_matrix(shape, coords, L)
+        g = rng.standard_normal(shape)
+        got = oracle.recompose_adjoint(g, coords, L)
+        want = (np.linalg.inv(D).T @ g.reshape(-1)).reshape(shape)
+        assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want)), shape
+
+
+@pytest.mark.parametrize("shape", [(17, 17, 17), (33, 9, 17), (65, 33), (129,)])
+def test_recompose_adjoint_identities(shape):
+    """<R y, g> = <y, R^T g> for random y, g, and R^T D^T g = (D R)^T g = g."""
+    rng = np.random.default_rng(43)
+    coords = rand_coords(rng, shape)
+    y = rng.standard_normal(shape)
+    g = rng.standard_normal(shape)
+    ry = oracle.recompose(y, coords)
+    lhs = np.sum(ry * g)
+    rhs = np.sum(y * oracle.recompose_adjoint(g, coords))
+    assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(ry * g))
+    back = oracle.recompose_adjoint(oracle.decompose_adjoint(g, coords), coords)
+    assert np.max(np.abs(back - g)) <= 1e-12 * np.max(np.abs(g))
