@@ -51,6 +51,15 @@ def _load():
         lib.oracle_class_map.argtypes = [ctypes.c_int, i64p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_class_map.restype = ctypes.c_int
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_quantize.argtypes = [ctypes.c_void_p, i32p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int,
+                                        ctypes.c_int, dp, i64p]
+        lib.oracle_quantize.restype = ctypes.c_int
+        lib.oracle_dequantize.argtypes = [i32p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int,
+                                          ctypes.c_int, dp]
+        lib.oracle_dequantize.restype = ctypes.c_int
+        lib.oracle_quant_bins.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+        lib.oracle_quant_bins.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -217,3 +226,53 @@ def recompose_level(y, level, coords=None, nlevels=-1):
     r = recompose(z, coords, L)
     s = 2 ** (L - level)
     return np.ascontiguousarray(r[tuple(slice(None, None, s) for _ in y.shape)])
+
+
+# ---- quantisation of the classes (Sec. V, lossy compression) -----------------
+# Reading (the paper names the stage, not the quantiser): per-class uniform
+# scalar quantiser, code = round-half-even(y / b_class) in the data's own
+# precision, clamped to +-(2^31 - 1) (NaN to 0); dequantised value
+# code * b_class in that precision.
+
+
+def _dtype_code(a):
+    if a.dtype == np.float32:
+        return 0
+    if a.dtype == np.float64:
+        return 1
+    raise TypeError("float32 or float64")
+
+
+def quant_bins(ndim, nlevels, tol):
+    """Bin widths (nlevels + 1) for a max-norm bound tol on the recomposed
+    field (derivation in oracle/mgr_oracle.c)."""
+    b = np.zeros(nlevels + 1, dtype=np.float64)
+    _check(_load().oracle_quant_bins(int(ndim), int(nlevels), float(tol), _dp(b)))
+    return b
+
+
+def quantize(y, bins, nlevels=-1, packed=False, shape=None):
+    """Codes (int32, same flat order as y) and the clamped count.  y is the
+    in-place layout (its own shape) or, with packed=True, the class-packed
+    layout of `shape`."""
+    y = np.ascontiguousarray(y)
+    shape = tuple(y.shape) if shape is None else tuple(shape)
+    b = np.ascontiguousarray(bins, dtype=np.float64)
+    q = np.zeros(y.shape, dtype=np.int32)
+    nc = ctypes.c_int64(0)
+    _check(_load().oracle_quantize(y.ctypes.data, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   _dtype_code(y), len(shape), _shape_arg(shape), int(nlevels), int(bool(packed)),
+                                   _dp(b), ctypes.byref(nc)))
+    return q, int(nc.value)
+
+
+def dequantize(q, bins, dtype, nlevels=-1, packed=False, shape=None):
+    """Values code * bin in `dtype` (numpy float32 or float64)."""
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    shape = tuple(q.shape) if shape is None else tuple(shape)
+    b = np.ascontiguousarray(bins, dtype=np.float64)
+    y = np.zeros(q.shape, dtype=dtype)
+    _check(_load().oracle_dequantize(q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), y.ctypes.data,
+                                     _dtype_code(y), len(shape), _shape_arg(shape), int(nlevels), int(bool(packed)),
+                                     _dp(b)))
+    return y

@@ -34,6 +34,7 @@
  */
 #include "mgr_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -729,5 +730,134 @@ int oracle_class_map(int ndim, const int64_t* shape, int nlevels, uint8_t* out)
         }
         out[idx++] = (uint8_t)((v >= nlevels) ? 0 : nlevels - v);
     } while (next_index(g.nd, j, g.n));
+    return 0;
+}
+
+/* ---- quantisation of the classes (Sec. V, lossy compression) -------------
+ * The paper moves MGARD's quantisation and dequantisation of the refactored
+ * classes onto the GPU but does not state the quantiser.  Reading taken: a
+ * uniform scalar quantiser per class.  An element y of class c (bin width
+ * b_c > 0) gets the code q = round-half-even(y / b_c), computed in the
+ * precision of the data (the bin width is first rounded to it), and is
+ * dequantised to q * b_c in that precision.  A rounded quotient that is NaN
+ * or outside +-(2^31 - 1) is clamped (NaN to 0) and counted.  In the
+ * in-place layout the class of an element is that of its node; in the
+ * class-packed layout it is the segment the element lies in. */
+
+/* Class of every element of the chosen layout (malloc'd; NULL on failure). */
+static uint8_t* element_classes(int ndim, const int64_t* shape, int nlevels, int packed, int64_t* total)
+{
+    grid_t g;
+    if (setup(&g, ndim, shape, NULL, &nlevels)) return NULL;
+    int64_t n = 1;
+    for (int d = 0; d < ndim; d++) n *= shape[d];
+    uint8_t* cls = (uint8_t*)malloc((size_t)n);
+    if (!cls) return NULL;
+    if (oracle_class_map(ndim, shape, nlevels, cls)) {
+        free(cls);
+        return NULL;
+    }
+    if (packed) {
+        /* segment c holds as many elements as there are nodes of class c */
+        int64_t count[256] = {0};
+        for (int64_t i = 0; i < n; i++) count[cls[i]]++;
+        int64_t i = 0;
+        for (int c = 0; c <= nlevels; c++)
+            for (int64_t k = 0; k < count[c]; k++) cls[i++] = (uint8_t)c;
+    }
+    *total = n;
+    return cls;
+}
+
+static int bins_ok(const double* bins, int nclasses)
+{
+    if (!bins) return 0;
+    for (int c = 0; c < nclasses; c++)
+        if (!(bins[c] > 0.0) || !isfinite(bins[c])) return 0;
+    return 1;
+}
+
+static int32_t clamp_code(double q, int64_t* nclamped)
+{
+    if (q != q) {
+        (*nclamped)++;
+        return 0;
+    }
+    if (q > 2147483647.0) {
+        (*nclamped)++;
+        return 2147483647;
+    }
+    if (q < -2147483647.0) {
+        (*nclamped)++;
+        return -2147483647;
+    }
+    return (int32_t)q;
+}
+
+int oracle_quantize(const void* y, int32_t* q, int dtype, int ndim, const int64_t* shape, int nlevels,
+                    int packed, const double* bins, int64_t* nclamped)
+{
+    int64_t n = 0, clamped = 0;
+    if (!y || !q || (dtype != 0 && dtype != 1)) return 1;
+    if (nlevels < 0) nlevels = oracle_max_levels(ndim, shape);
+    if (nlevels < 0) return 2;
+    if (!bins_ok(bins, nlevels + 1)) return 1;
+    uint8_t* cls = element_classes(ndim, shape, nlevels, packed, &n);
+    if (!cls) return 6;
+    for (int64_t i = 0; i < n; i++) {
+        if (dtype == 0) {
+            const float b = (float)bins[cls[i]];
+            const float r = ((const float*)y)[i] / b;
+            q[i] = clamp_code((double)rintf(r), &clamped);
+        } else {
+            const double b = bins[cls[i]];
+            const double r = ((const double*)y)[i] / b;
+            q[i] = clamp_code(rint(r), &clamped);
+        }
+    }
+    free(cls);
+    if (nclamped) *nclamped = clamped;
+    return 0;
+}
+
+int oracle_dequantize(const int32_t* q, void* y, int dtype, int ndim, const int64_t* shape, int nlevels,
+                      int packed, const double* bins)
+{
+    int64_t n = 0;
+    if (!y || !q || (dtype != 0 && dtype != 1)) return 1;
+    if (nlevels < 0) nlevels = oracle_max_levels(ndim, shape);
+    if (nlevels < 0) return 2;
+    if (!bins_ok(bins, nlevels + 1)) return 1;
+    uint8_t* cls = element_classes(ndim, shape, nlevels, packed, &n);
+    if (!cls) return 6;
+    for (int64_t i = 0; i < n; i++) {
+        if (dtype == 0)
+            ((float*)y)[i] = (float)q[i] * (float)bins[cls[i]];
+        else
+            ((double*)y)[i] = (double)q[i] * bins[cls[i]];
+    }
+    free(cls);
+    return 0;
+}
+
+/* Bin widths for a bound tol on the largest pointwise error of the
+ * recomposition (exact arithmetic).  A change e of the class-0 values moves
+ * the recomposed values by at most max|e|: the later steps only interpolate
+ * it, with nonnegative weights that sum to one.  A change e of class l >= 1
+ * moves them by (I - Q_{l-1}) applied to the level-l interpolant of e (the
+ * correction subtracts the projection of the coefficients, Eq. (1)), then
+ * interpolated again, so by at most (1 + |Q|) max|e|, where |Q| is the
+ * largest row sum of the projection's nodal matrix: the tensor product of
+ * one-dimensional projections onto piecewise-linear functions, each of which
+ * has a max-norm bound of 3 on any mesh, so |Q| <= 3^d.  Splitting tol
+ * evenly over the L + 1 classes with errors of half a bin:
+ *   b_0 = 2 tol / (L + 1),   b_l = 2 tol / ((L + 1) (1 + 3^d)). */
+int oracle_quant_bins(int ndim, int nlevels, double tol, double* bins)
+{
+    if (!bins || ndim < 1 || ndim > MAXD || nlevels < 0 || !(tol > 0.0) || !isfinite(tol)) return 1;
+    double k = 1.0;
+    for (int d = 0; d < ndim; d++) k *= 3.0;
+    for (int c = 0; c <= nlevels; c++)
+        bins[c] = 2.0 * tol / ((double)(nlevels + 1) * (c == 0 ? 1.0 : 1.0 + k));
     return 0;
 }

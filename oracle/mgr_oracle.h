@@ -68,6 +68,23 @@ int oracle_correction_level(double* f, int ndim, const int64_t* shape,
 int oracle_class_map(int ndim, const int64_t* shape, int nlevels,
                      uint8_t* out);
 
+/* Quantisation of a refactored array (the quantisation stage of the lossy
+ * compression workflow, Sec. V): per-class uniform scalar quantiser, code
+ * q = round-half-even(y / b_c) in the data's precision (dtype 0 = float,
+ * 1 = double; y is float* or double*), b_c = bins[class] rounded to that
+ * precision, clamped to +-(2^31 - 1) (NaN to 0); *nclamped (may be NULL)
+ * receives the number clamped.  packed = 0: y is in the in-place layout;
+ * packed = 1: the class-packed layout (class c is the c-th segment).
+ * bins: host, nlevels + 1 positive finite widths (nlevels -1 = full). */
+int oracle_quantize(const void* y, int32_t* q, int dtype, int ndim, const int64_t* shape, int nlevels,
+                    int packed, const double* bins, int64_t* nclamped);
+/* y = q * b_c in the data's precision, same conventions. */
+int oracle_dequantize(const int32_t* q, void* y, int dtype, int ndim, const int64_t* shape, int nlevels,
+                      int packed, const double* bins);
+/* Bin widths (nlevels + 1) for a bound tol on the pointwise error of the
+ * recomposed field (exact arithmetic); see mgr_oracle.c. */
+int oracle_quant_bins(int ndim, int nlevels, double tol, double* bins);
+
 #ifdef __cplusplus
 }
 #endif

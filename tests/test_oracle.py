@@ -429,3 +429,127 @@ def test_recompose_adjoint_identities(shape):
     assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(ry * g))
     back = oracle.recompose_adjoint(oracle.decompose_adjoint(g, coords), coords)
     assert np.max(np.abs(back - g)) <= 1e-12 * np.max(np.abs(g))
+
+
+# ---- quantisation of the classes (Sec. V, lossy compression) ----------------
+# Reading: per-class uniform scalar quantiser, round half to even in the data's
+# precision, codes clamped to +-(2^31 - 1).  Pins: exact multiples and ties of
+# power-of-two bins (decided exactly by the definition), the half-bin bound in
+# exact rational arithmetic, the class used per element (revealed through
+# bins 2^-c), clamping, and the recomposed max-norm bound of the bin rule.
+
+
+def _brute_class(idx, L):
+    v = L
+    for i in idx:
+        if i == 0:
+            continue
+        t = 0
+        while i % 2 == 0:
+            i //= 2
+            t += 1
+        v = min(v, t)
+    return 0 if v >= L else L - v
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_quantize_exact_multiples_and_ties(dt):
+    shape, L = (9, 17), 3
+    bins = np.array([2.0 ** -c for c in range(L + 1)]) * 0.25
+    rng = np.random.default_rng(41)
+    k = rng.integers(-1000, 1000, size=shape)
+    cls = np.array([_brute_class(i, L) for i in np.ndindex(*shape)]).reshape(shape)
+    b = bins[cls]
+    q, nc = oracle.quantize((k * b).astype(dt), bins, L)
+    assert nc == 0 and np.array_equal(q, k)
+    # exact ties k + 1/2 go to the even neighbour
+    q, _ = oracle.quantize(((k + 0.5) * b).astype(dt), bins, L)
+    want = np.where(k % 2 == 0, k, k + 1)
+    assert np.array_equal(q, want)
+    y = oracle.dequantize(k.astype(np.int32), bins, dt, L)
+    assert y.dtype == dt and np.array_equal(y, (k * b).astype(dt))
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_quantize_half_bin_bound_exact(dt):
+    from fractions import Fraction
+    shape, L = (17, 9), 2
+    rng = np.random.default_rng(42)
+    y = rng.standard_normal(shape).astype(dt)
+    bins = np.array([0.013, 0.0071, 0.0029])
+    q, _ = oracle.quantize(y, bins, L)
+    for idx in list(np.ndindex(*shape))[::7]:
+        b = Fraction(float(dt(bins[_brute_class(idx, L)])))
+        err = abs(Fraction(float(y[idx])) - q[idx] * b)
+        # the quotient is rounded to the data's precision before rounding to
+        # an integer, which can add one unit of its last place
+        slack = Fraction(float(abs(y[idx]))) * Fraction(2 * float(np.finfo(dt).eps))
+        assert err <= b / 2 + slack, (idx, err, b)
+
+
+@pytest.mark.parametrize("packed", [False, True])
+def test_quantize_class_per_element(packed):
+    """With bins 2^-c and unit values the code is 2^c: the class that each
+    element was quantised with, against the brute-force class definition
+    (in-place layout) or the class segments of the packed layout."""
+    shape, L = (9, 5, 17), 2
+    bins = np.array([2.0 ** -c for c in range(L + 1)])
+    ones = np.ones(int(np.prod(shape)) if packed else shape)
+    q, _ = oracle.quantize(ones, bins, L, packed=packed, shape=shape)
+    got = np.log2(q.astype(np.float64)).astype(int).reshape(-1)
+    if packed:
+        sizes = [int(np.prod([(n - 1) // 2 ** (L - l) + 1 for n in shape])) for l in range(L + 1)]
+        counts = [sizes[0]] + [sizes[l] - sizes[l - 1] for l in range(1, L + 1)]
+        want = np.concatenate([np.full(c, l) for l, c in enumerate(counts)])
+    else:
+        want = np.array([_brute_class(i, L) for i in np.ndindex(*shape)])
+    assert np.array_equal(got, want)
+
+
+def test_quantize_clamps_and_counts():
+    shape, L = (5, 5), 1
+    y = np.zeros(shape)
+    y[0, 1], y[1, 1], y[2, 3] = 1e300, -1e300, np.nan
+    y[3, 0] = 2147483646.0  # representable, not clamped
+    q, nc = oracle.quantize(y, np.ones(L + 1), L)
+    assert nc == 3
+    assert q[0, 1] == 2147483647 and q[1, 1] == -2147483647 and q[2, 3] == 0 and q[3, 0] == 2147483646
+    y32 = np.zeros(shape, dtype=np.float32)
+    y32[4, 4] = 2.0 ** 31  # rounds to 2^31 in float32: clamped
+    q, nc = oracle.quantize(y32, np.ones(L + 1), L)
+    assert nc == 1 and q[4, 4] == 2147483647
+
+
+def test_one_dimensional_projection_max_norm_at_most_three():
+    """The bin rule assumes |Q| <= 3 per dimension for the nodal matrix of
+    the L2 projection onto the next coarser piecewise-linear space (largest
+    row sum), on any mesh; checked on random meshes with spacings spread over
+    five orders of magnitude."""
+    rng = np.random.default_rng(43)
+    worst = 0.0
+    for t in range(120):
+        m = 2 ** int(rng.integers(1, 6)) + 1
+        h = np.exp(rng.uniform(-6, 6, m - 1)) if t % 2 else rng.uniform(0.5, 1.5, m - 1)
+        x = np.concatenate([[0.0], np.cumsum(h)])
+        xc = x[::2]
+        P = dense_ref.hat_eval_1d(x, xc)
+        Q = np.linalg.solve(dense_ref.fe_mass_1d(xc), P.T @ dense_ref.fe_mass_1d(x))
+        worst = max(worst, float(np.abs(P @ Q).sum(axis=1).max()))
+    assert worst <= 3.0
+
+
+@pytest.mark.parametrize("shape", [(257,), (33, 65), (17, 9, 33)])
+@pytest.mark.parametrize("nonuniform", [False, True])
+@pytest.mark.parametrize("tol", [1e-1, 1e-3])
+def test_quant_bins_bound_recomposition_error(shape, nonuniform, tol):
+    """Recomposing the dequantised classes stays within tol of the field
+    (max norm), for the bin widths of quant_bins."""
+    rng = np.random.default_rng(44)
+    coords = rand_coords(rng, shape) if nonuniform else None
+    u = rng.standard_normal(shape)
+    L = oracle.max_levels(shape)
+    bins = oracle.quant_bins(len(shape), L, tol)
+    q, nc = oracle.quantize(oracle.decompose(u, coords, L), bins, L)
+    assert nc == 0
+    r = oracle.recompose(oracle.dequantize(q, bins, np.float64, L), coords, L)
+    assert np.max(np.abs(r - u)) <= tol
