@@ -140,11 +140,22 @@ def coefficients_level(u, k, coords=None):
     return _run("oracle_coefficients_level", u, coords, k)
 
 
+def level_size(n, k):
+    """Nodes of the level-k grid (k steps from the finest) along a dimension
+    of n nodes: the multiples of 2^k below n and the last node."""
+    return ((n - 2) >> k) + 2
+
+
+def level_indices(n, k):
+    """Full-grid indices of that level grid, in order."""
+    return np.minimum(np.arange(level_size(n, k), dtype=np.int64) << k, n - 1)
+
+
 def load_vector_level(u, k, coords=None):
     """Load vector f = R M vec(C) of level step k, packed (Sec. II-A.2)."""
     lib = _load()
     a = np.ascontiguousarray(u, dtype=np.float64)
-    cshape = tuple(((n - 1) >> (k + 1)) + 1 for n in a.shape)
+    cshape = tuple(level_size(n, k + 1) for n in a.shape)
     f = np.zeros(cshape, dtype=np.float64)
     cp, keep = _coords_arg(a.shape, coords)
     _check(lib.oracle_load_vector_level(_dp(a), _dp(f), a.ndim, _shape_arg(a.shape), cp, int(k)))
@@ -224,8 +235,7 @@ def recompose_level(y, level, coords=None, nlevels=-1):
     cm = class_map(y.shape, L)
     z = np.where(cm <= level, y, 0.0)
     r = recompose(z, coords, L)
-    s = 2 ** (L - level)
-    return np.ascontiguousarray(r[tuple(slice(None, None, s) for _ in y.shape)])
+    return np.ascontiguousarray(r[np.ix_(*[level_indices(n, L - level) for n in y.shape])])
 
 
 # ---- quantisation of the classes (Sec. V, lossy compression) -----------------

@@ -31,6 +31,15 @@
  *    the coarse nodes (Sec. II-A.1), never sequential 1D updates.
  *  - Dimensions are processed last-to-first for the load vector and the
  *    solve (rows first, Sec. II-A "Overall process").
+ *  - Sizes (the paper's grids are all 2^k + 1 nodes per dimension and it is
+ *    silent on others): a level grid of m nodes along a dimension keeps as
+ *    coarse nodes its even positions and its last node, so both boundary
+ *    nodes stay on every level and a level of even length has no fine node
+ *    in its last interval.  The level-k grid along a dimension of n nodes is
+ *    then {i : 2^k divides i} plus the node n - 1, of size
+ *    ceil((n - 1) / 2^k) + 1; for n = 2^K + 1 this is the usual stride-2^k
+ *    grid.  All dimensions coarsen together; the full decomposition stops
+ *    when the shortest level grid has 3 nodes.
  */
 #include "mgr_oracle.h"
 
@@ -67,11 +76,13 @@ static double node_x(const grid_t* g, int d, int64_t i)
     return (double)i;
 }
 
-static int log2_exact(int64_t v)
+/* Level steps after which a dimension of n >= 3 nodes is down to 2 nodes:
+ * the smallest K with 2^K >= n - 1. */
+static int steps_to_two(int64_t n)
 {
     int k = 0;
-    while (((int64_t)1 << k) < v) k++;
-    return (((int64_t)1 << k) == v) ? k : -1;
+    while (((int64_t)1 << k) < n - 1) k++;
+    return k;
 }
 
 int oracle_max_levels(int ndim, const int64_t* shape)
@@ -80,8 +91,7 @@ int oracle_max_levels(int ndim, const int64_t* shape)
     int kmin = 64;
     for (int d = 0; d < ndim; d++) {
         if (shape[d] < 3) return -2;
-        int k = log2_exact(shape[d] - 1);
-        if (k < 1) return -2;
+        int k = steps_to_two(shape[d]);
         if (k < kmin) kmin = k;
     }
     return kmin - 1;
@@ -110,10 +120,32 @@ static int setup(grid_t* g, int ndim, const int64_t* shape,
     return 0;
 }
 
-/* Level-grid size along d at step k. */
+/* Level-grid size along d at step k: ceil((n - 1) / 2^k) + 1. */
 static int64_t lsize(const grid_t* g, int d, int k)
 {
-    return ((g->n[d] - 1) >> k) + 1;
+    return ((g->n[d] - 2) >> k) + 2;
+}
+
+/* Full-grid index along d of level index j at step k: the j-th multiple of
+ * 2^k, or the last node. */
+static int64_t lpos(const grid_t* g, int d, int k, int64_t j)
+{
+    const int64_t i = j << k;
+    return (i < g->n[d] - 1) ? i : g->n[d] - 1;
+}
+
+/* Whether level index j of a level grid of m nodes is fine-only (odd and
+ * not the last node); every other index is coarse. */
+static int is_fine(int64_t j, int64_t m)
+{
+    return (j & 1) && j != m - 1;
+}
+
+/* Coarse-grid index of a coarse level index j (m nodes): j / 2, or the last
+ * coarse index for the last node. */
+static int64_t coarse_index(int64_t j, int64_t m)
+{
+    return (j == m - 1) ? m / 2 : j / 2;
 }
 
 /* Coordinates of the level grid at step k along d (length lsize). */
@@ -122,7 +154,7 @@ static double* level_coords(const grid_t* g, int d, int k)
     int64_t m = lsize(g, d, k);
     double* y = (double*)malloc(sizeof(double) * (size_t)m);
     if (!y) return NULL;
-    for (int64_t j = 0; j < m; j++) y[j] = node_x(g, d, j << k);
+    for (int64_t j = 0; j < m; j++) y[j] = node_x(g, d, lpos(g, d, k, j));
     return y;
 }
 
@@ -137,7 +169,7 @@ static double interp_a(const double* y, int64_t j)
 static int64_t offset_of(const grid_t* g, const int64_t* j, int k)
 {
     int64_t o = 0;
-    for (int d = 0; d < g->nd; d++) o += (j[d] << k) * g->st[d];
+    for (int d = 0; d < g->nd; d++) o += lpos(g, d, k, j[d]) * g->st[d];
     return o;
 }
 
@@ -175,24 +207,28 @@ static void mass_mult(const double* v, double* out, int64_t m, const double* y)
     }
 }
 
-/* out = P^T w: restriction from m fine nodes to (m+1)/2 coarse nodes. */
+/* out = P^T w: restriction from m fine nodes to the m / 2 + 1 coarse
+ * nodes.  Coarse node i (level index f: 2i, or the last node) collects
+ * itself and its fine-only neighbours with their interpolation weights. */
 static void restrict_t(const double* w, double* out, int64_t m, const double* y)
 {
-    int64_t mc = (m + 1) / 2;
+    int64_t mc = m / 2 + 1;
     for (int64_t i = 0; i < mc; i++) {
-        double s = w[2 * i];
-        if (2 * i - 1 >= 0) s += interp_a(y, 2 * i - 1) * w[2 * i - 1];
-        if (2 * i + 1 < m) s += (1.0 - interp_a(y, 2 * i + 1)) * w[2 * i + 1];
+        int64_t f = (i == mc - 1) ? m - 1 : 2 * i;
+        double s = w[f];
+        if (f - 1 >= 0 && is_fine(f - 1, m)) s += interp_a(y, f - 1) * w[f - 1];
+        if (f + 1 < m && is_fine(f + 1, m)) s += (1.0 - interp_a(y, f + 1)) * w[f + 1];
         out[i] = s;
     }
 }
 
-/* out = P z: piecewise-linear prolongation from (m+1)/2 coarse nodes. */
+/* out = P z: piecewise-linear prolongation from m / 2 + 1 coarse nodes to
+ * m fine nodes. */
 static void prolong(const double* z, double* out, int64_t m, const double* y)
 {
     for (int64_t j = 0; j < m; j++) {
-        if ((j & 1) == 0) {
-            out[j] = z[j / 2];
+        if (!is_fine(j, m)) {
+            out[j] = z[coarse_index(j, m)];
         } else {
             double a = interp_a(y, j);
             out[j] = (1.0 - a) * z[(j - 1) / 2] + a * z[(j + 1) / 2];
@@ -230,15 +266,14 @@ static int thomas(double* f, int64_t mc, const double* yc)
 enum { OP_MASSTRANS, OP_SOLVE, OP_PROLONG_MASS };
 
 /* Apply a 1D operator to every fibre along dimension d of a packed array A
- * of shape sh, writing packed B whose size along d is m_out. */
+ * of shape sh, writing packed B whose size along d is m_out (the coarse size
+ * for OP_MASSTRANS, the fine size for OP_PROLONG_MASS, sh[d] for OP_SOLVE). */
 static int along_dim(const double* A, double* B, int nd, const int64_t* sh,
-                     int d, int op, const double* y)
+                     int d, int op, const double* y, int64_t m_out)
 {
     int64_t outer = 1, inner = 1, m_in = sh[d];
     for (int e = 0; e < d; e++) outer *= sh[e];
     for (int e = d + 1; e < nd; e++) inner *= sh[e];
-    int64_t m_out = (op == OP_MASSTRANS) ? (m_in + 1) / 2
-                  : (op == OP_PROLONG_MASS) ? 2 * m_in - 1 : m_in;
     int64_t mx = (m_in > m_out) ? m_in : m_out;
     int64_t nfib = outer * inner;
     int rc = 0;
@@ -299,7 +334,7 @@ static int stage_coefficients(double* u, const grid_t* g, int k)
             int64_t j[MAXD];
             index_of(nd, idx, m, j);
             int odd[MAXD], t = 0;
-            for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
+            for (int d = 0; d < nd; d++) { odd[d] = is_fine(j[d], m[d]); t += odd[d]; }
             if (t == 0) continue;
             double interp = 0.0;
             for (int mask = 0; mask < (1 << nd); mask++) {
@@ -343,7 +378,7 @@ static int stage_load_vector(const double* u, double* f, const grid_t* g, int k)
         int64_t idx = 0;
         do {
             int coarse = 1;
-            for (int d = 0; d < nd; d++) if (j[d] & 1) coarse = 0;
+            for (int d = 0; d < nd; d++) if (is_fine(j[d], m[d])) coarse = 0;
             a[idx++] = coarse ? 0.0 : u[offset_of(g, j, k)];
         } while (next_index(nd, j, m));
         int64_t sh[MAXD];
@@ -351,9 +386,9 @@ static int stage_load_vector(const double* u, double* f, const grid_t* g, int k)
         for (int d = nd - 1; d >= 0 && rc == 0; d--) {
             double* y = level_coords(g, d, k);
             if (!y) { rc = 6; break; }
-            rc = along_dim(a, b, nd, sh, d, OP_MASSTRANS, y);
+            rc = along_dim(a, b, nd, sh, d, OP_MASSTRANS, y, sh[d] / 2 + 1);
             free(y);
-            sh[d] = (sh[d] + 1) / 2;
+            sh[d] = sh[d] / 2 + 1;
             double* t = a; a = b; b = t;
         }
         if (rc == 0) {
@@ -381,7 +416,7 @@ static int stage_correction(double* f, const grid_t* g, int k, int reverse)
         int d = reverse ? s : nd - 1 - s;
         double* yc = level_coords(g, d, k + 1);
         if (!yc) { rc = 6; break; }
-        rc = along_dim(f, tmp, nd, sh, d, OP_SOLVE, yc);
+        rc = along_dim(f, tmp, nd, sh, d, OP_SOLVE, yc, sh[d]);
         free(yc);
         memcpy(f, tmp, sizeof(double) * (size_t)Vc);
     }
@@ -422,7 +457,7 @@ static int stage_interpolate_add(double* u, const grid_t* g, int k)
             int64_t j[MAXD];
             index_of(nd, idx, m, j);
             int odd[MAXD], t = 0;
-            for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
+            for (int d = 0; d < nd; d++) { odd[d] = is_fine(j[d], m[d]); t += odd[d]; }
             if (t == 0) continue;
             double interp = 0.0;
             for (int mask = 0; mask < (1 << nd); mask++) {
@@ -533,9 +568,9 @@ int oracle_decompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
         for (int d = 0; d < nd && rc == 0; d++) {
             double* y = level_coords(&g, d, k);
             if (!y) { rc = 6; break; }
-            rc = along_dim(a, b, nd, sh, d, OP_PROLONG_MASS, y);
+            rc = along_dim(a, b, nd, sh, d, OP_PROLONG_MASS, y, m[d]);
             free(y);
-            sh[d] = 2 * sh[d] - 1;
+            sh[d] = m[d];
             double* t = a; a = b; b = t;
         }
         if (rc == 0) {
@@ -547,7 +582,7 @@ int oracle_decompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
                 idx = 0;
                 do {
                     int fine = 0;
-                    for (int d = 0; d < nd; d++) if (j[d] & 1) fine = 1;
+                    for (int d = 0; d < nd; d++) if (is_fine(j[d], m[d])) fine = 1;
                     if (fine) g_arr[offset_of(&g, j, k)] += a[idx];
                     idx++;
                 } while (next_index(nd, j, m));
@@ -556,7 +591,7 @@ int oracle_decompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
                 memset(j, 0, sizeof(j));
                 do {
                     int odd[MAXD], t = 0;
-                    for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
+                    for (int d = 0; d < nd; d++) { odd[d] = is_fine(j[d], m[d]); t += odd[d]; }
                     if (t == 0) continue;
                     double vf = g_arr[offset_of(&g, j, k)];
                     for (int mask = 0; mask < (1 << nd); mask++) {
@@ -620,7 +655,7 @@ int oracle_recompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
              * corners with the interpolation weights. */
             do {
                 int odd[MAXD], t = 0;
-                for (int d = 0; d < nd; d++) { odd[d] = (int)(j[d] & 1); t += odd[d]; }
+                for (int d = 0; d < nd; d++) { odd[d] = is_fine(j[d], m[d]); t += odd[d]; }
                 if (t == 0) continue;
                 double vf = g_arr[offset_of(&g, j, k)];
                 for (int mask = 0; mask < (1 << nd); mask++) {
@@ -651,8 +686,8 @@ int oracle_recompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
             int64_t sh[MAXD];
             for (int d = 0; d < nd; d++) sh[d] = mc[d];
             for (int d = 0; d < nd && rc == 0; d++) {
-                rc = along_dim(a, b, nd, sh, d, OP_PROLONG_MASS, y[d]);
-                sh[d] = 2 * sh[d] - 1;
+                rc = along_dim(a, b, nd, sh, d, OP_PROLONG_MASS, y[d], m[d]);
+                sh[d] = m[d];
                 double* tt = a; a = b; b = tt;
             }
             /* g_f' = g_f - t at the fine-only nodes */
@@ -661,7 +696,7 @@ int oracle_recompose_adjoint(double* g_arr, int ndim, const int64_t* shape,
                 idx = 0;
                 do {
                     int fine = 0;
-                    for (int d = 0; d < nd; d++) if (j[d] & 1) fine = 1;
+                    for (int d = 0; d < nd; d++) if (is_fine(j[d], m[d])) fine = 1;
                     if (fine) g_arr[offset_of(&g, j, k)] -= a[idx];
                     idx++;
                 } while (next_index(nd, j, m));
@@ -724,7 +759,8 @@ int oracle_class_map(int ndim, const int64_t* shape, int nlevels, uint8_t* out)
         int v = nlevels;
         for (int d = 0; d < g.nd; d++) {
             int vd = 0;
-            if (j[d] == 0) continue;
+            /* the first and last nodes are on every level grid */
+            if (j[d] == 0 || j[d] == g.n[d] - 1) continue;
             while (((j[d] >> vd) & 1) == 0) vd++;
             if (vd < v) v = vd;
         }

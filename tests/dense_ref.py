@@ -140,3 +140,78 @@ def coefficients_dense(u, coords, k):
     view = out[sl]
     view[fine] = (v - pi)[fine]
     return out
+
+
+# ---- any sizes ---------------------------------------------------------------
+# The same definitions on nested grids of any size n >= 3 per dimension: the
+# level grid l (paper numbering, L finest) along a dimension of n nodes is
+# the set of indices that are multiples of 2^(L - l), together with the last
+# index n - 1 (so both boundary nodes are on every level).  For n = 2^K + 1
+# this is the usual stride-2^(L - l) grid.  Written from the sets alone.
+
+
+def level_index_set(n, L, l):
+    s = 2 ** (L - l)
+    return sorted(set(range(0, n, s)) | {n - 1})
+
+
+def full_levels_nested(shape):
+    """Level steps until the shortest level grid has 3 nodes."""
+    def steps(n):
+        k = 0
+        while len(level_index_set(n, k, 0)) > 3:
+            k += 1
+        return k
+    return min(steps(n) for n in shape)
+
+
+def projection_values_nested(u, coords, L, l):
+    shape = u.shape
+    xs = [axis_coords(n, None if coords is None else coords[d]) for d, n in enumerate(shape)]
+    sets = [level_index_set(n, L, l) for n in shape]
+    xl = [x[idx] for x, idx in zip(xs, sets)]
+    M_L = kron_all([fe_mass_1d(x) for x in xs])
+    B = kron_all([hat_eval_1d(x, y) for x, y in zip(xs, xl)])
+    M_l = kron_all([fe_mass_1d(y) for y in xl])
+    q = np.linalg.solve(M_l, B.T @ (M_L @ u.reshape(-1)))
+    return q.reshape(tuple(len(y) for y in xl)), sets, xl
+
+
+def decompose_dense_nested(u, coords=None, L=None):
+    """Eq. (1) on the nested grids above: Q_0 u at the coarsest nodes, and
+    (I - Pi_{l-1}) Q_l u at the nodes of level l that are not on level l - 1."""
+    u = np.asarray(u, dtype=np.float64)
+    shape = u.shape
+    if L is None or L < 0:
+        L = full_levels_nested(shape)
+    out = np.zeros(shape)
+    q0, sets0, _ = projection_values_nested(u, coords, L, 0)
+    out[np.ix_(*sets0)] = q0
+    for l in range(1, L + 1):
+        q, sets, xl = projection_values_nested(u, coords, L, l)
+        csets = [level_index_set(n, L, l - 1) for n in shape]
+        # positions of the coarse nodes inside the level-l grid
+        cpos = [[s.index(i) for i in c] for s, c in zip(sets, csets)]
+        xc = [y[p] for y, p in zip(xl, cpos)]
+        interp = kron_all([hat_eval_1d(y, yc) for y, yc in zip(xl, xc)])
+        qc = q[np.ix_(*cpos)]
+        detail = q - (interp @ qc.reshape(-1)).reshape(q.shape)
+        fine = np.zeros(q.shape, dtype=bool)
+        grids = np.meshgrid(*[np.array([i not in c for i in s]) for s, c in zip(sets, csets)], indexing="ij")
+        for g in grids:
+            fine |= g
+        view = out[np.ix_(*sets)]
+        view[fine] = detail[fine]
+        out[np.ix_(*sets)] = view
+    return out
+
+
+def class_map_nested(shape, L):
+    """Class of every node: 0 on the coarsest grid, else the first level l
+    whose grid contains it."""
+    out = np.zeros(shape, dtype=np.uint8)
+    member = [[set(level_index_set(n, L, l)) for l in range(L + 1)] for n in shape]
+    for idx in np.ndindex(*shape):
+        c = next(l for l in range(L + 1) if all(i in member[d][l] for d, i in enumerate(idx)))
+        out[idx] = c
+    return out

@@ -314,9 +314,9 @@ def test_coefficients_level_is_u_minus_interpolant(shape, k, nonuniform):
 def test_error_codes():
     u = np.zeros((9, 9))
     with pytest.raises(oracle.OracleError, match="shape"):
-        oracle.decompose(np.zeros((10, 9)))
-    with pytest.raises(oracle.OracleError, match="shape"):
         oracle.decompose(np.zeros((2, 9)))
+    with pytest.raises(oracle.OracleError, match="levels"):
+        oracle.decompose(np.zeros((10, 9)), None, 5)  # 10 -> 6 -> 4 -> 3 -> 2: four steps at most
     with pytest.raises(oracle.OracleError, match="levels"):
         oracle.decompose(u, None, 4)
     with pytest.raises(oracle.OracleError, match="coordinates"):
@@ -324,6 +324,7 @@ def test_error_codes():
     assert oracle.max_levels((9, 9)) == 2
     assert oracle.max_levels((513, 513, 513)) == 8
     assert oracle.max_levels((1025, 1025, 257)) == 7
+    assert oracle.max_levels((10, 9)) == 2 and oracle.max_levels((100, 37)) == 5 and oracle.max_levels((3, 7)) == 0
     # nlevels = 0 is the identity
     v = np.arange(81.0).reshape(9, 9)
     assert np.array_equal(oracle.decompose(v, None, 0), v)
@@ -553,3 +554,95 @@ def test_quant_bins_bound_recomposition_error(shape, nonuniform, tol):
     assert nc == 0
     r = oracle.recompose(oracle.dequantize(q, bins, np.float64, L), coords, L)
     assert np.max(np.abs(r - u)) <= tol
+
+
+# ---- sizes other than 2^k + 1 ---------------------------------------------
+# Reading (the paper's grids are all 2^k + 1 per dimension): the level grid of
+# a dimension of n nodes keeps the multiples of 2^step and the last node.
+# Pinned by the dense nested-grid L2 projection written from those sets alone
+# (dense_ref.decompose_dense_nested), which equals dense_ref.decompose_dense
+# on 2^k + 1 sizes.
+
+ANY = [(10,), (7,), (4,), (12, 6), (9, 10), (6, 9, 5), (4, 5, 6), (5, 4, 3, 6), (3, 7, 4, 5)]
+
+
+@pytest.mark.parametrize("shape", ANY)
+@pytest.mark.parametrize("nonuniform", [False, True])
+def test_any_size_matches_dense_nested_projection(shape, nonuniform):
+    rng = np.random.default_rng(abs(hash((shape, nonuniform, "any"))) % 2**32)
+    coords = rand_coords(rng, shape) if nonuniform else None
+    u = rng.standard_normal(shape)
+    full = oracle.max_levels(shape)
+    assert full == dense_ref.full_levels_nested(shape)
+    for L in sorted({1, full, full + 1}):
+        if L < 1:
+            continue
+        got = oracle.decompose(u, coords, L)
+        want = dense_ref.decompose_dense_nested(u, coords, L)
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(u)), (shape, L)
+        assert np.array_equal(oracle.class_map(shape, L), dense_ref.class_map_nested(shape, L))
+        back = oracle.recompose(got, coords, L)
+        assert np.max(np.abs(back - u)) <= 1e-13 * np.max(np.abs(u))
+
+
+def test_nested_dense_equals_dyadic_dense():
+    rng = np.random.default_rng(51)
+    for shape in [(9,), (5, 9), (5, 5, 9)]:
+        coords = rand_coords(rng, shape)
+        u = rng.standard_normal(shape)
+        for L in (1, oracle.max_levels(shape)):
+            a = dense_ref.decompose_dense(u, coords, L)
+            b = dense_ref.decompose_dense_nested(u, coords, L)
+            assert np.max(np.abs(a - b)) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(10,), (6, 7), (5, 6, 4)])
+def test_any_size_multilinear_input_zero_classes(shape):
+    """A field in V_k (the multilinear interpolant of values on the level-k
+    grid) has zero classes above k and its coarsest values unchanged."""
+    rng = np.random.default_rng(52)
+    coords = rand_coords(rng, shape)
+    L = oracle.max_levels(shape)
+    for k in range(L):
+        sets = [dense_ref.level_index_set(n, L, k) for n in shape]
+        xs = [np.asarray(c) for c in coords]
+        B = dense_ref.kron_all([dense_ref.hat_eval_1d(x, x[s]) for x, s in zip(xs, sets)])
+        u = (B @ rng.standard_normal(int(np.prod([len(s) for s in sets])))).reshape(shape)
+        y = oracle.decompose(u, coords, L)
+        cm = oracle.class_map(shape, L)
+        assert np.max(np.abs(y[cm > k])) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(6, 7), (5, 4, 3)])
+def test_any_size_adjoints_equal_dense_transposes(shape):
+    rng = np.random.default_rng(53)
+    coords = rand_coords(rng, shape)
+    L = oracle.max_levels(shape)
+    N = int(np.prod(shape))
+    D = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        D[:, j] = dense_ref.decompose_dense_nested(e.reshape(shape), coords, L).reshape(-1)
+    Dinv_t = np.linalg.inv(D).T
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        got = oracle.decompose_adjoint(e.reshape(shape), coords, L).reshape(-1)
+        assert np.max(np.abs(got - D[j, :])) <= 1e-12 * max(1.0, np.max(np.abs(D)))
+        got = oracle.recompose_adjoint(e.reshape(shape), coords, L).reshape(-1)
+        assert np.max(np.abs(got - Dinv_t[:, j])) <= 1e-11 * max(1.0, np.max(np.abs(Dinv_t)))
+
+
+@pytest.mark.parametrize("shape", [(10,), (6, 9), (5, 6, 4)])
+def test_any_size_progressive_is_the_projection(shape):
+    rng = np.random.default_rng(54)
+    coords = rand_coords(rng, shape)
+    u = rng.standard_normal(shape)
+    L = oracle.max_levels(shape)
+    y = oracle.decompose(u, coords, L)
+    for l in range(L + 1):
+        want, _, _ = dense_ref.projection_values_nested(u, coords, L, l)
+        got = oracle.recompose_level(y, l, coords, L)
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(u))
