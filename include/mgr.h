@@ -11,6 +11,18 @@
  *    contiguous dimension).  One plane of the array (the contiguous row in
  *    1-D and 2-D, shape[1] * shape[2] elements in 3-D) must stay below 2 GiB:
  *    the kernels address within a plane with 32-bit byte offsets.
+ *  - General grids: mgr_decompose, mgr_recompose, mgr_prepare,
+ *    mgr_max_levels and mgr_class_map also take `ndim` up to 4 and any
+ *    sizes >= 3 (the paper's grids are 2^k + 1 and it says nothing of
+ *    others).  Along each dimension the level-k grid is then the nodes at
+ *    multiples of 2^k plus the last node, ceil((n - 1) / 2^k) + 1 nodes: a
+ *    level grid of m nodes keeps its even positions and its last one as
+ *    coarse nodes.  The full decomposition stops when the shortest level grid
+ *    has 3 nodes (L = min_d ceil(log2(n_d - 1)) - 1), and 0..L+1 level steps
+ *    are accepted.  A node's class is L minus the finest level k <= L whose
+ *    grid holds it in every dimension.  These shapes run per-stage kernels
+ *    (no per-plane addressing limit); the other entry points refuse them with
+ *    MGR_ERR_SHAPE.
  *  - `coords` describes node positions (nonuniform structured grids,
  *    Sec. II-A): NULL, or coords[d] == NULL, means uniform spacing along d;
  *    otherwise coords[d] is a HOST array of shape[d] strictly increasing
@@ -55,15 +67,17 @@ typedef enum { MGR_F32 = 0, MGR_F64 = 1 } mgr_dtype;
 enum {
     MGR_OK = 0,
     MGR_ERR_ARG = 1,      /* null pointer, bad ndim or dtype */
-    MGR_ERR_SHAPE = 2,    /* a size is not 2^k + 1 with k >= 1, or a plane is 2 GiB or more */
-    MGR_ERR_LEVELS = 3,   /* nlevels outside -1, 0..min_d k_d */
+    MGR_ERR_SHAPE = 2,    /* a size below 3; for the entry points limited to 2^k + 1 grids, a
+                             size not 2^k + 1 or ndim 4; a plane of 2 GiB or more */
+    MGR_ERR_LEVELS = 3,   /* nlevels outside -1, 0..L+1 (L the full count) */
     MGR_ERR_COORDS = 4,   /* coordinates not strictly increasing or not finite */
     MGR_ERR_HIP = 5,      /* a HIP runtime call or kernel launch failed */
     MGR_ERR_ALLOC = 6,    /* device allocation failed or exceeds MGR_WORKSPACE_MAX */
     MGR_ERR_CAPTURE = 7   /* would allocate while `stream` is being captured */
 };
 
-/* Full level count for a shape (min_d k_d - 1), or minus a status. */
+/* Full level count for a shape (min_d k_d - 1 for 2^k + 1 sizes; general
+ * grids as above), or minus a status. */
 int mgr_max_levels(int ndim, const int64_t* shape);
 
 /* Decomposition (refactoring), Sec. II-A, Eq. (1)-(2): for each level step,
@@ -160,6 +174,42 @@ int mgr_unpack_classes(const void* src, void* dst, int dtype, int ndim, const in
 int mgr_recompose_level(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
                         const double* const* coords, int nlevels, int level, int packed, void* stream);
 
+/* ---- quantisation of the classes ----------------------------------------
+ * The lossy-compression use of the refactoring quantises each coefficient
+ * class with its own bin width and stores the integer codes (Sec. V; the
+ * paper names the stage, not the quantiser).  Quantiser: uniform scalar per
+ * class c with bin width b_c (one value per class 0..L, host doubles,
+ * positive and finite):
+ *     code  = round-half-even(y / b_c)  computed in the data's precision
+ *             (b_c rounded to it first; IEEE division),
+ *     value = code * b_c                 in the data's precision.
+ * A rounded quotient that is NaN, or beyond +-(2^31 - 1), is clamped (NaN to
+ * 0, else to +-(2^31 - 1)) and counted.  The class of an element is that of
+ * its node (packed = 0, in-place node order) or of the segment it lies in
+ * (packed = 1, class-packed layout); shape and nlevels are those of the
+ * decomposition.  Device pointers, prod(shape) elements and int32 codes,
+ * asynchronous on `stream`. */
+
+/* Bin widths for a bound tol > 0 on the largest pointwise error of the
+ * recomposition of the dequantised classes (exact arithmetic):
+ * b_0 = 2 tol / (L + 1), b_c = 2 tol / ((L + 1)(1 + 3^ndim)) for c >= 1.
+ * The class-0 values reach the field only through interpolation (max-norm
+ * nonexpansive); a class-c error reaches it through the level-c interpolant
+ * minus its L2 projection onto the coarser space (Eq. (1)), at most
+ * (1 + 3^ndim) times its size.  Writes nlevels + 1 values to the host array
+ * bins. */
+int mgr_quant_bins(int ndim, int nlevels, double tol, double* bins);
+
+/* codes <- quantised src.  nclamped: NULL, or a device pointer to one
+ * unsigned 64-bit counter that receives the number of clamped codes (set to
+ * zero, then accumulated, in stream order). */
+int mgr_quantize(const void* src, int32_t* codes, int dtype, int ndim, const int64_t* shape, int nlevels,
+                 int packed, const double* bins, unsigned long long* nclamped, void* stream);
+
+/* dst <- dequantised codes. */
+int mgr_dequantize(const int32_t* codes, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+                   int packed, const double* bins, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* mgr_status_string(int status);
 
@@ -214,17 +264,59 @@ int mgr_batch_plan_create(int nfields, const int* ndim, const int64_t* const* sh
  * (out of place).  Calls on one plan must be ordered on one stream. */
 int mgr_batch_decompose(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream);
 
-/* Autotuner: ranks the candidate chunk lengths (coarse planes per streaming
- * item, 2..128) by a transaction model, times the best top_k on these fields
- * (4 runs each, synchronously) and keeps the fastest.  Overwrites dst. */
+/* Autotuner (the model-then-measure search of Sec. III-C): for the plan's
+ * launch form (mgr_batch_set_mode) it times three probe chunk lengths
+ * (coarse planes per streaming item: 2, 16, 128) on these fields, fits a
+ * transaction model time = a + x * bytes + y * items to them (bytes: the
+ * streaming items' traffic with their re-read plane halos; items: streaming
+ * items), ranks every chunk length 2..128 by the fitted model, times the best
+ * top_k, and keeps the fastest chunk measured.  Synchronous; overwrites
+ * dst. */
 int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream,
                        int top_k);
 
-/* Current configuration: chunk length, launches per call, work items. */
+/* The launch form the plan uses (0 waves, 1 persistent) and the fitted model
+ * constants of the last autotune of each form: model[3 * form + i] = a (ms),
+ * x (ms per byte), y (ms per streaming item) (zeros for a form not tuned). */
+int mgr_batch_tuning(const mgr_batch_plan* plan, int* persistent, double* model);
+
+/* Current configuration: chunk length, kernel launches per call (besides
+ * the pointer upload), work items. */
 int mgr_batch_config(const mgr_batch_plan* plan, int* chunk, int* launches, int64_t* items);
 
 /* Sets the chunk length (1..128) and rebuilds the work items. */
 int mgr_batch_set_config(mgr_batch_plan* plan, int chunk);
+
+/* Launch form of later mgr_batch_decompose calls on the plan (results are
+ * bit for bit the same either way):
+ *   persistent = 0: one launch per wave of items (the default);
+ *   persistent = 1: one launch for every item of every field, whose
+ *     workgroups take items from a queue in order and wait, before each, for
+ *     the items it depends on (the previous stage of the same field): fields
+ *     advance independently of each other.  Then one launch for the small
+ *     coarse levels, as in the other form.  Each wait is bounded by
+ *     poll_limit polls (0: the default, 2^20, a thousand times any legitimate wait on the
+ *     96-field workload);
+ *     a wait that runs out aborts the whole launch, which then ends, and
+ *     mgr_batch_check reports it.  The queue words live in the plan, so the
+ *     calls (and graph replays) on one plan must be ordered on one stream. */
+int mgr_batch_set_mode(mgr_batch_plan* plan, int persistent, unsigned poll_limit);
+
+/* Synchronises the device and reports whether the plan's last persistent run
+ * aborted (MGR_ERR_HIP, with the work item in mgr_last_error) or not. */
+int mgr_batch_check(mgr_batch_plan* plan);
+
+/* Host check of the persistent form's scheduling protocol: builds the work
+ * items, waves and dependency groups of a batch of these fields on the host
+ * alone (no device is used) and runs the same queue functions the kernel
+ * runs on nthreads host threads standing in for workgroups, each item
+ * "executed" as a random delay.  The thread that takes item stall_item
+ * (>= 0; -1 for none) stops without finishing it, as a workgroup that never
+ * completes would.  Writes out[0] items run, out[1] items that started before
+ * the items they depend on had finished, out[2] the error word (1 + the item
+ * whose wait ran out, 0 if none), out[3] items never taken. */
+int mgr_batch_queue_check(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int dtype,
+                          int chunk, int nthreads, unsigned poll_limit, int stall_item, uint64_t seed, int64_t* out);
 
 /* Frees the plan (hipFree waits for work still using it). */
 void mgr_batch_plan_destroy(mgr_batch_plan* plan);

@@ -24,8 +24,9 @@ __all__ = [
     "mgr_class_map", "class_masks", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
     "decompose", "recompose", "decompose_adjoint", "recompose_adjoint", "Decompose", "Recompose",
-    "kernel_classes", "BatchPlan",
+    "kernel_classes", "BatchPlan", "batch_queue_check",
     "class_offsets", "pack_classes", "unpack_classes", "recompose_level",
+    "quant_bins", "quantize", "dequantize",
 ]
 
 
@@ -196,6 +197,77 @@ def recompose_level(src, level, shape=None, coords=None, nlevels=-1, packed=Fals
     return out
 
 
+def quant_bins(ndim, nlevels, tol):
+    """Per-class bin widths (nlevels + 1 doubles) for a bound tol on the
+    largest pointwise error of the recomposed field (mgr_quant_bins)."""
+    import ctypes
+    b = np.zeros(int(nlevels) + 1, dtype=np.float64)
+    _lib.check(_lib.load().mgr_quant_bins(int(ndim), int(nlevels), float(tol),
+                                          b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return b
+
+
+def _bins_arg(bins, L):
+    import ctypes
+    b = np.ascontiguousarray(np.asarray(bins, dtype=np.float64))
+    if b.shape != (L + 1,):
+        raise ValueError(f"one bin width per class: {L + 1} values")
+    return b, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def quantize(y, bins, shape=None, nlevels=-1, packed=False, codes=None, count=True):
+    """int32 codes of the classes of a refactored array y (in-place layout,
+    or class-packed with packed=True and the field's shape).  Returns
+    (codes, clamped) with clamped a one-element int64 GPU tensor holding the
+    number of clamped codes (None with count=False)."""
+    torch = _torch()
+    _check(y, "y")
+    shape = tuple(y.shape) if shape is None else tuple(int(n) for n in shape)
+    L = mgr_max_levels(shape) if int(nlevels) < 0 else int(nlevels)
+    if y.numel() != int(np.prod(shape)):
+        raise ValueError("y does not hold prod(shape) elements")
+    if codes is None:
+        codes = torch.empty(tuple(y.shape), dtype=torch.int32, device=y.device)
+    _check(codes, "codes")
+    if codes.numel() != y.numel() or codes.dtype != torch.int32 or codes.device != y.device:
+        raise ValueError("codes must be int32 with as many elements as y, on its device")
+    b, bp = _bins_arg(bins, L)
+    clamped = torch.empty(1, dtype=torch.int64, device=y.device) if count else None
+    stream = torch.cuda.current_stream(y.device).cuda_stream
+    with torch.cuda.device(y.device):
+        st = _lib.load().mgr_quantize(y.data_ptr(), codes.data_ptr(), _dtype_code(y), len(shape),
+                                      _lib.shape_arg(shape), int(nlevels), 1 if packed else 0, bp,
+                                      clamped.data_ptr() if count else None, stream)
+    del b
+    _lib.check(st)
+    return codes, clamped
+
+
+def dequantize(codes, bins, dtype, shape=None, nlevels=-1, packed=False, out=None):
+    """Dequantised classes (code * bin width, in `dtype`) from int32 codes."""
+    torch = _torch()
+    _check(codes, "codes")
+    if codes.dtype != torch.int32:
+        raise ValueError("codes must be int32")
+    shape = tuple(codes.shape) if shape is None else tuple(int(n) for n in shape)
+    L = mgr_max_levels(shape) if int(nlevels) < 0 else int(nlevels)
+    if codes.numel() != int(np.prod(shape)):
+        raise ValueError("codes does not hold prod(shape) elements")
+    if out is None:
+        out = torch.empty(tuple(codes.shape), dtype=dtype, device=codes.device)
+    _check(out, "out")
+    if out.numel() != codes.numel() or out.device != codes.device:
+        raise ValueError("out must have as many elements as codes, on its device")
+    b, bp = _bins_arg(bins, L)
+    stream = torch.cuda.current_stream(codes.device).cuda_stream
+    with torch.cuda.device(codes.device):
+        st = _lib.load().mgr_dequantize(codes.data_ptr(), out.data_ptr(), _dtype_code(out), len(shape),
+                                        _lib.shape_arg(shape), int(nlevels), 1 if packed else 0, bp, stream)
+    del b
+    _lib.check(st)
+    return out
+
+
 def mgr_bench_copy(src, dst):
     """Single-pass copy kernel (achievable-bandwidth calibration)."""
     _check(src, "src")
@@ -329,6 +401,25 @@ Decompose = _LazyFunction("Decompose")
 Recompose = _LazyFunction("Recompose")
 
 
+def batch_queue_check(shapes, dtype_code=MGR_F32, nlevels=None, chunk=8, nthreads=8, poll_limit=0,
+                      stall_item=-1, seed=0):
+    """Runs the persistent batch's scheduling protocol for these field shapes
+    on host threads (mgr_batch_queue_check; no device needed).  Returns
+    (items run, items started before their dependencies finished, error
+    word, items never taken)."""
+    import ctypes
+    shapes = [tuple(int(n) for n in s) for s in shapes]
+    nf = len(shapes)
+    nd = (ctypes.c_int * nf)(*[len(s) for s in shapes])
+    shp = [_lib.shape_arg(s) for s in shapes]
+    shp_p = (ctypes.POINTER(ctypes.c_int64) * nf)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_int64)) for a in shp])
+    nl = None if nlevels is None else (ctypes.c_int * nf)(*[int(x) for x in nlevels])
+    out = (ctypes.c_int64 * 4)()
+    _lib.check(_lib.load().mgr_batch_queue_check(nf, nd, shp_p, nl, int(dtype_code), int(chunk), int(nthreads),
+                                                 int(poll_limit), int(stall_item), int(seed), out))
+    return tuple(int(v) for v in out)
+
+
 class BatchPlan:
     """Plan for decomposing many independent fields together: one launch per
     wave of work items (``mgr_batch_plan_create`` / ``mgr_batch_decompose``).
@@ -400,6 +491,25 @@ class BatchPlan:
 
     def set_config(self, chunk):
         _lib.check(_lib.load().mgr_batch_set_config(self._h, int(chunk)))
+
+    def tuning(self):
+        """(persistent form in use, fitted model per form: {"waves": (a_ms,
+        ms_per_byte, ms_per_item), "persistent": (...)}) after autotune."""
+        import ctypes
+        p = ctypes.c_int(0)
+        m = (ctypes.c_double * 6)()
+        _lib.check(_lib.load().mgr_batch_tuning(self._h, ctypes.byref(p), m))
+        return bool(p.value), {"waves": tuple(m[0:3]), "persistent": tuple(m[3:6])}
+
+    def set_mode(self, persistent, poll_limit=0):
+        """persistent=True: one queue-driven launch for all items (see
+        mgr_batch_set_mode); poll_limit bounds each dependency wait."""
+        _lib.check(_lib.load().mgr_batch_set_mode(self._h, 1 if persistent else 0, int(poll_limit)))
+
+    def check(self):
+        """Synchronises and raises MgrError if the last persistent run
+        aborted."""
+        _lib.check(_lib.load().mgr_batch_check(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -55,6 +55,13 @@ def load():
     lib.mgr_recompose_level.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, vp]
     lib.mgr_recompose_level.restype = ctypes.c_int
+    lib.mgr_quant_bins.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.mgr_quant_bins.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.mgr_quantize.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, dp, vp, vp]
+    lib.mgr_quantize.restype = ctypes.c_int
+    lib.mgr_dequantize.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, dp, vp]
+    lib.mgr_dequantize.restype = ctypes.c_int
     lib.mgr_status_string.argtypes = [ctypes.c_int]
     lib.mgr_status_string.restype = ctypes.c_char_p
     lib.mgr_last_error.argtypes = []
@@ -87,6 +94,15 @@ def load():
     lib.mgr_batch_config.restype = ctypes.c_int
     lib.mgr_batch_set_config.argtypes = [vp, ctypes.c_int]
     lib.mgr_batch_set_config.restype = ctypes.c_int
+    lib.mgr_batch_tuning.argtypes = [vp, i32p, ctypes.POINTER(ctypes.c_double)]
+    lib.mgr_batch_tuning.restype = ctypes.c_int
+    lib.mgr_batch_set_mode.argtypes = [vp, ctypes.c_int, ctypes.c_uint]
+    lib.mgr_batch_set_mode.restype = ctypes.c_int
+    lib.mgr_batch_check.argtypes = [vp]
+    lib.mgr_batch_check.restype = ctypes.c_int
+    lib.mgr_batch_queue_check.argtypes = [ctypes.c_int, i32p, ctypes.POINTER(i64p), i32p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_uint, ctypes.c_int, ctypes.c_uint64, i64p]
+    lib.mgr_batch_queue_check.restype = ctypes.c_int
     lib.mgr_batch_plan_destroy.argtypes = [vp]
     lib.mgr_batch_plan_destroy.restype = None
     _lib = lib

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libmgr.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("mgr_api.cpp", "mgr_kernels.hip", "mgr_stream.hip", "mgr_recon.hip", "mgr_solve.hip", "mgr_tail.hip",
-            "mgr_batch.hip", "mgr_adjoint.hip", "mgr_packed.hip")]
+            "mgr_batch.hip", "mgr_adjoint.hip", "mgr_packed.hip", "mgr_quant.hip", "mgr_general.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -255,8 +256,9 @@ SolveTab build_solve(const std::vector<double>& yc)
         t.sup[(size_t)i] = hc(i);
         diag[(size_t)i] = 2.0 * (hc(i - 1) + hc(i));
     }
-    // n - 1 is a power of two, so it is a multiple of kSeg once >= kSeg
-    t.S = (n - 1 >= kSeg) ? (int)((n - 1) / kSeg) : 1;
+    // one segment up to kSlot nodes, else segments of kSeg (the last one
+    // shorter when kSeg does not divide n - 1; for 2^k + 1 sizes it does)
+    t.S = (n <= kSlot) ? 1 : (int)((n - 1 + kSeg - 1) / kSeg);
     const int S = t.S;
     const size_t P = (size_t)S * kSlot;
     t.L.assign(P, 0.0);
@@ -1022,10 +1024,10 @@ int run_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 //   out_f = g_f + (M P) y at the level grid's fine-only nodes, written to their
 //        final places in dst (the adjoint kernel; the values it also writes at
 //        coarse positions are overwritten by the coarser steps),
-// and finally the coarsest grid W_L to its nodes.  In place is safe: each
-// step reads the input's coarse values (into W_{k+1}) before the expansion
-// overwrites them, and a fine output depends on the input at its own node
-// only.
+// and finally the coarsest grid W_L to its nodes.  In place, each step reads
+// the input's coarse values (into W_{k+1}) before the expansion overwrites
+// them; the finest step's expansion, whose tiles also read halo inputs of
+// their neighbours, writes to the workspace and is copied back.
 template <typename T>
 int run_recompose_adjoint(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
@@ -1066,17 +1068,405 @@ int run_recompose_adjoint(const Plan& p, const void* src_, void* dst_, hipStream
         MGR_TRY(launch_add_split<T>(g, gc, F, W, F, st), "combine launch");
         int rc = solve_all<T>(p, k, true, F, st);
         if (rc) return rc;
+        // in place, the finest step's tiles would re-read halo inputs that a
+        // neighbouring tile has already overwritten: it goes through the
+        // workspace and is copied back (its coarse positions are overwritten
+        // by the coarser steps anyway)
+        const bool via_tb = (k == 0) && (const void*)src == (const void*)dst;
+        T* out = via_tb ? ws + p.Tb : dst;
+        const View3 ov = via_tb ? full_view(p) : level_view(p, k);
         MGR_TRY(timed(KC_ADJOINT, k, st,
-                      [&] {
-                          return launch_stream_adjoint<T>(g, gv, F, W, cv, dst, level_view(p, k), tables_of<T>(p, k),
-                                                          st);
-                      }),
+                      [&] { return launch_stream_adjoint<T>(g, gv, F, W, cv, out, ov, tables_of<T>(p, k), st); }),
                 "recomposition adjoint level launch");
+        if (via_tb) {
+            const size_t bytes = (size_t)(p.n[0] * p.n[1] * p.n[2]) * sizeof(T);
+            MGR_TRY(hipMemcpyAsync(dst, ws + p.Tb, bytes, hipMemcpyDeviceToDevice, st), "adjoint copy-out");
+        }
     }
     View3 cl = level_view(p, L);
     MGR_TRY(timed(KC_COPY_VIEW, L, st,
                   [&] { return launch_copy_view<T>(ws + p.Woff[(size_t)L], nullptr, packed(cl.n), dst, cl, st); }),
             "coarsest scatter");
+    return MGR_OK;
+}
+
+// ---- general grids: 1..4 dimensions of any size >= 3 -------------------------
+// Level grids keep, along each dimension, the multiples of 2^k and the last
+// node: the level-k grid of a dimension of n nodes has ceil((n - 1) / 2^k) + 1
+// nodes, and a level grid of m nodes has m / 2 + 1 coarse nodes (its even
+// positions and its last one).  For 2^k + 1 sizes this is the usual nested
+// grid, which the fused path handles; the general path (mgr_general.hip)
+// runs any other shape, and every shape of four dimensions.
+int64_t gen_lsize(int64_t n, int k) { return ((n - 2) >> k) + 2; }
+
+// Level steps after which a dimension of n >= 3 nodes is down to two nodes.
+int gen_steps_to_two(int64_t n)
+{
+    int k = 0;
+    while (((int64_t)1 << k) < n - 1) k++;
+    return k;
+}
+
+bool dyadic_shape(int ndim, const int64_t* shape)
+{
+    if (ndim < 1 || ndim > kMaxDim) return false;
+    for (int d = 0; d < ndim; d++)
+        if (shape[d] < 3 || log2_exact(shape[d] - 1) < 1) return false;
+    return true;
+}
+
+// Validation for every shape the library accepts: ndim 1..4, every size >= 3;
+// the full decomposition stops when the shortest level grid has 3 nodes, and
+// 0 .. full + 1 level steps are accepted.  (For 2^k + 1 sizes this is the
+// same as validate.)
+int validate_general(int dtype, int ndim, const int64_t* shape, const double* const* coords, int* nlevels)
+{
+    if (dtype != MGR_F32 && dtype != MGR_F64) return fail(MGR_ERR_ARG, "dtype must be MGR_F32 or MGR_F64");
+    if (ndim < 1 || ndim > kGenMaxDim) return fail(MGR_ERR_ARG, "ndim must be 1..4");
+    if (!shape) return fail(MGR_ERR_ARG, "shape is NULL");
+    if (dyadic_shape(ndim, shape)) return validate(dtype, ndim, shape, coords, nlevels);
+    int kmin = 64;
+    for (int d = 0; d < ndim; d++) {
+        if (shape[d] < 3)
+            return fail(MGR_ERR_SHAPE, "shape[" + std::to_string(d) + "] = " + std::to_string(shape[d]) + " is below 3");
+        kmin = std::min(kmin, gen_steps_to_two(shape[d]));
+    }
+    if (*nlevels == -1) *nlevels = kmin - 1;
+    if (*nlevels < 0 || *nlevels > kmin)
+        return fail(MGR_ERR_LEVELS, "nlevels = " + std::to_string(*nlevels) + " outside 0.." + std::to_string(kmin) +
+                                        " (or -1)");
+    if (coords) {
+        for (int d = 0; d < ndim; d++) {
+            const double* x = coords[d];
+            if (!x) continue;
+            for (int64_t i = 0; i < shape[d]; i++)
+                if (!std::isfinite(x[i]) || (i > 0 && !(x[i] > x[i - 1])))
+                    return fail(MGR_ERR_COORDS, "coords[" + std::to_string(d) +
+                                                    "] not finite and strictly increasing at " + std::to_string(i));
+        }
+    }
+    return MGR_OK;
+}
+
+// Interpolation weights and load-vector rows of a level grid of any length m
+// (positions y).  Coarse node i sits at fine position f(i) = 2i, or m - 1 for
+// the last one; K = P^T M row i covers fine nodes f(i) - 2 .. f(i) + 2.
+struct GenDimTab {
+    std::vector<double> wl, wh, K;
+};
+GenDimTab build_dim_general(const std::vector<double>& y)
+{
+    const int64_t m = (int64_t)y.size(), mc = m / 2 + 1;
+    auto fine = [m](int64_t j) { return (j & 1) && j != m - 1; };
+    GenDimTab t;
+    t.wl.assign((size_t)m, 0.0);
+    t.wh.assign((size_t)m, 0.0);
+    for (int64_t j = 1; j < m; j++) {
+        if (!fine(j)) continue;
+        const double a = (y[(size_t)j] - y[(size_t)(j - 1)]) / (y[(size_t)(j + 1)] - y[(size_t)(j - 1)]);
+        t.wl[(size_t)j] = 1.0 - a;
+        t.wh[(size_t)j] = a;
+    }
+    auto h = [&](int64_t j) { return (j >= 0 && j < m - 1) ? y[(size_t)(j + 1)] - y[(size_t)j] : 0.0; };
+    auto M = [&](int64_t r, int64_t c) {
+        if (c == r) return 2.0 * (h(r - 1) + h(r));
+        if (c == r - 1) return h(r - 1);
+        if (c == r + 1) return h(r);
+        return 0.0;
+    };
+    t.K.assign((size_t)(5 * mc), 0.0);
+    for (int64_t i = 0; i < mc; i++) {
+        const int64_t f = (i == mc - 1) ? m - 1 : 2 * i;
+        // P(l, i): 1 at the coarse node itself, the interpolation weight of a
+        // fine neighbour towards it
+        auto P = [&](int64_t l) {
+            if (l == f) return 1.0;
+            if (l < 0 || l >= m || !fine(l)) return 0.0;
+            return (l == f - 1) ? t.wh[(size_t)l] : t.wl[(size_t)l];
+        };
+        for (int tt = 0; tt < 5; tt++) {
+            const int64_t c = f - 2 + tt;
+            if (c < 0 || c >= m) continue;
+            double s = 0.0;
+            for (int64_t l = f - 1; l <= f + 1; l++)
+                if (l >= 0 && l < m) s += P(l) * M(l, c);
+            t.K[(size_t)(5 * i + tt)] = s;
+        }
+    }
+    return t;
+}
+
+struct GenLevelHost {
+    int64_t m[kGenMaxDim], mc[kGenMaxDim];
+    size_t wl[kGenMaxDim], wh[kGenMaxDim], K[kGenMaxDim];
+    size_t solve[kGenMaxDim][10];  // L, U, IP, A, B, ssub, ssup, sl, sip, su
+    int S[kGenMaxDim];
+};
+
+struct GenPlan {
+    int device = 0, dtype = 0, nd = 0, nlevels = 0;
+    int64_t n[kGenMaxDim] = {1, 1, 1, 1}, st[kGenMaxDim] = {0, 0, 0, 0};
+    std::vector<GenLevelHost> lv;  // level steps 0 .. L - 1
+    void* tables = nullptr;
+    void* ws = nullptr;
+    size_t tables_bytes = 0, ws_bytes = 0;
+    std::vector<size_t> Woff;  // packed level grids W_k, k = 1..L (index k)
+    size_t A = 0, B = 0, Yb = 0;
+};
+std::map<std::string, std::unique_ptr<GenPlan>> g_gen_plans;
+
+void free_gen_plan(GenPlan& p)
+{
+    if (p.tables) (void)hipFree(p.tables);
+    if (p.ws) (void)hipFree(p.ws);
+    p.tables = p.ws = nullptr;
+}
+
+template <typename T>
+int build_gen_plan(GenPlan& p, const double* const* coords)
+{
+    const int nd = p.nd, L = p.nlevels;
+    std::vector<std::vector<double>> X((size_t)nd);
+    for (int d = 0; d < nd; d++) X[(size_t)d] = axis_positions(p.n[d], coords ? coords[d] : nullptr);
+    std::vector<T> host;
+    p.lv.resize((size_t)L);
+    size_t big = 0, yb = 64;
+    for (int k = 0; k < L; k++) {
+        GenLevelHost& ly = p.lv[(size_t)k];
+        int64_t box[kGenMaxDim];
+        for (int d = 0; d < nd; d++) {
+            const int64_t m = gen_lsize(p.n[d], k);
+            ly.m[d] = m;
+            ly.mc[d] = m / 2 + 1;
+            std::vector<double> y((size_t)m), yc((size_t)ly.mc[d]);
+            for (int64_t j = 0; j < m; j++) y[(size_t)j] = X[(size_t)d][(size_t)std::min(j << k, p.n[d] - 1)];
+            for (int64_t i = 0; i < ly.mc[d]; i++) yc[(size_t)i] = y[(size_t)(i == ly.mc[d] - 1 ? m - 1 : 2 * i)];
+            GenDimTab t = build_dim_general(y);
+            push_table(host, t.wl, &ly.wl[d]);
+            push_table(host, t.wh, &ly.wh[d]);
+            push_table(host, t.K, &ly.K[d]);
+            SolveTab sv = build_solve(yc);
+            ly.S[d] = sv.S;
+            const std::vector<double>* parts[10] = {&sv.L, &sv.U, &sv.IP, &sv.A, &sv.B,
+                                                    &sv.ssub, &sv.ssup, &sv.sl, &sv.sip, &sv.su};
+            for (int q = 0; q < 10; q++) push_table(host, *parts[q], &ly.solve[d][q]);
+            box[d] = m;
+        }
+        // load-vector passes, last dimension first: intermediate sizes
+        for (int d = nd - 1; d >= 0; d--) {
+            box[d] = ly.mc[d];
+            int64_t v = 1;
+            for (int e = 0; e < nd; e++) v *= box[e];
+            big = std::max(big, (size_t)v);
+        }
+        // three-phase solve scratch: two values per segment and fibre
+        int64_t vc = 1;
+        for (int e = 0; e < nd; e++) vc *= ly.mc[e];
+        for (int d = 0; d < nd; d++) yb = std::max(yb, (size_t)(2 * (int64_t)ly.S[d] * (vc / ly.mc[d])) + 64);
+    }
+    const size_t al = 256 / sizeof(T);
+    size_t off = 0;
+    p.Woff.assign((size_t)L + 1, 0);
+    for (int k = 1; k <= L; k++) {
+        int64_t v = 1;
+        for (int d = 0; d < nd; d++) v *= gen_lsize(p.n[d], k);
+        p.Woff[(size_t)k] = off;
+        off = align_up(off + (size_t)v, al);
+    }
+    p.A = off; off = align_up(off + big, al);
+    p.B = off; off = align_up(off + big, al);
+    p.Yb = off; off = align_up(off + yb, al);
+    p.ws_bytes = off * sizeof(T);
+    p.tables_bytes = host.size() * sizeof(T);
+    if (p.ws_bytes + p.tables_bytes > workspace_cap())
+        return fail(MGR_ERR_ALLOC, "workspace of " + std::to_string(p.ws_bytes) + " bytes exceeds MGR_WORKSPACE_MAX");
+    if (p.tables_bytes) {
+        hipError_t e = hipMalloc(&p.tables, p.tables_bytes);
+        if (e != hipSuccess) {
+            p.tables = nullptr;
+            return fail(MGR_ERR_ALLOC, std::string("hipMalloc tables: ") + hipGetErrorString(e));
+        }
+        e = hipMemcpy(p.tables, host.data(), p.tables_bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload tables");
+    }
+    if (p.ws_bytes) {
+        hipError_t e = hipMalloc(&p.ws, p.ws_bytes);
+        if (e != hipSuccess) {
+            p.ws = nullptr;
+            return fail(MGR_ERR_ALLOC, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+        }
+    }
+    return MGR_OK;
+}
+
+int get_gen_plan(int dtype, int ndim, const int64_t* shape, const double* const* coords, int nlevels,
+                 hipStream_t st, bool check_capture, GenPlan** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const std::string key = plan_key(dev, dtype, ndim, shape, coords, nlevels);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_gen_plans.find(key);
+    if (it != g_gen_plans.end()) {
+        *out = it->second.get();
+        return MGR_OK;
+    }
+    if (check_capture && capturing(st))
+        return fail(MGR_ERR_CAPTURE, "problem not prepared and the stream is capturing; call mgr_prepare first");
+    auto p = std::make_unique<GenPlan>();
+    p->device = dev;
+    p->dtype = dtype;
+    p->nd = ndim;
+    p->nlevels = nlevels;
+    int64_t s = 1;
+    for (int d = ndim - 1; d >= 0; d--) {
+        p->n[d] = shape[d];
+        p->st[d] = s;
+        s *= shape[d];
+    }
+    int rc = (dtype == MGR_F32) ? build_gen_plan<float>(*p, coords) : build_gen_plan<double>(*p, coords);
+    if (rc) {
+        free_gen_plan(*p);
+        return rc;
+    }
+    *out = p.get();
+    g_gen_plans.emplace(key, std::move(p));
+    return MGR_OK;
+}
+
+// Device view of level step k (k = L: sizes only, for the coarsest grid).
+template <typename T>
+GenLevel<T> gen_level(const GenPlan& p, int k)
+{
+    GenLevel<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nd = p.nd;
+    const T* tb = (const T*)p.tables;
+    for (int d = 0; d < p.nd; d++) {
+        a.n[d] = p.n[d];
+        a.st[d] = p.st[d];
+        a.m[d] = gen_lsize(p.n[d], k);
+        a.mc[d] = a.m[d] / 2 + 1;
+        if (k < p.nlevels) {
+            const GenLevelHost& ly = p.lv[(size_t)k];
+            a.wl[d] = tb + ly.wl[d];
+            a.wh[d] = tb + ly.wh[d];
+            a.K[d] = tb + ly.K[d];
+        }
+    }
+    return a;
+}
+
+// z of level step k into the plan's A or B buffer: the load vector of the
+// level grid's coefficients (read from y at their nodes), then the solves;
+// returns the buffer.
+template <typename T>
+int gen_correction(const GenPlan& p, int k, const T* y, hipStream_t st, T** zout)
+{
+    T* ws = (T*)p.ws;
+    const GenLevel<T> a = gen_level<T>(p, k);
+    const GenLevelHost& ly = p.lv[(size_t)k];
+    const int nd = p.nd;
+    GenPass ps;
+    std::memset(&ps, 0, sizeof(ps));
+    for (int d = 0; d < nd; d++) ps.in[d] = ps.out[d] = ly.m[d];
+    T* bufs[2] = {ws + p.A, ws + p.B};
+    const T* in = nullptr;
+    T* out = nullptr;
+    for (int s = 0; s < nd; s++) {
+        const int d = nd - 1 - s;
+        ps.d = d;
+        ps.full = (s == 0);
+        for (int e = 0; e < nd; e++) ps.in[e] = ps.out[e];
+        ps.out[d] = ly.mc[d];
+        out = bufs[s & 1];
+        MGR_TRY(timed(KC_STREAM_LOAD, k, st, [&] { return launch_gen_masstrans<T>(in, y, out, a, ps, k, st); }),
+                "load-vector launch");
+        in = out;
+    }
+    const T* tb = (const T*)p.tables;
+    for (int s = 0; s < nd; s++) {
+        const int d = nd - 1 - s;
+        int64_t inner = 1, outer = 1;
+        for (int e = d + 1; e < nd; e++) inner *= ly.mc[e];
+        for (int e = 0; e < d; e++) outer *= ly.mc[e];
+        SolveTables<T> t;
+        const T** f[10] = {&t.L, &t.U, &t.IP, &t.A, &t.B, &t.ssub, &t.ssup, &t.sl, &t.sip, &t.su};
+        for (int q = 0; q < 10; q++) *f[q] = tb + ly.solve[d][q];
+        t.S = ly.S[d];
+        MGR_TRY(timed(KC_SOLVE, k, st,
+                      [&] { return launch_solve_fibres<T>(out, ly.mc[d], inner, outer, t, ws + p.Yb, st); }),
+                "solve launch");
+    }
+    *zout = out;
+    return MGR_OK;
+}
+
+template <typename T>
+int run_gen_decompose(const GenPlan& p, const void* src_, void* dst_, hipStream_t st)
+{
+    const int L = p.nlevels;
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    T* ws = (T*)p.ws;
+    int64_t N = 1;
+    for (int d = 0; d < p.nd; d++) N *= p.n[d];
+    if (L == 0) {
+        if (src != dst) MGR_TRY(hipMemcpyAsync(dst, src, (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, st), "copy");
+        return MGR_OK;
+    }
+    T* z = nullptr;
+    for (int k = 0; k < L; k++) {
+        const GenLevel<T> a = gen_level<T>(p, k);
+        T* Wk = (k == 0) ? nullptr : ws + p.Woff[(size_t)k];
+        T* Wn = ws + p.Woff[(size_t)k + 1];
+        MGR_TRY(timed(KC_COEF, k, st, [&] { return launch_gen_coef<T>(src, Wk, dst, Wn, a, k, st); }),
+                "coefficient launch");
+        int rc = gen_correction<T>(p, k, dst, st, &z);
+        if (rc) return rc;
+        int64_t vc = 1;
+        for (int d = 0; d < p.nd; d++) vc *= a.mc[d];
+        MGR_TRY(launch_gen_axpy<T>(Wn, z, vc, T(1), st), "correction launch");
+    }
+    const GenLevel<T> aL = gen_level<T>(p, L);
+    MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                  [&] { return launch_gen_scatter<T>(dst, ws + p.Woff[(size_t)L], nullptr, aL, L, true, st); }),
+            "coarsest scatter");
+    return MGR_OK;
+}
+
+template <typename T>
+int run_gen_recompose(const GenPlan& p, const void* src_, void* dst_, hipStream_t st)
+{
+    const int L = p.nlevels;
+    const T* src = (const T*)src_;
+    T* dst = (T*)dst_;
+    T* ws = (T*)p.ws;
+    int64_t N = 1;
+    for (int d = 0; d < p.nd; d++) N *= p.n[d];
+    if (L == 0) {
+        if (src != dst) MGR_TRY(hipMemcpyAsync(dst, src, (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, st), "copy");
+        return MGR_OK;
+    }
+    const GenLevel<T> aL = gen_level<T>(p, L);
+    MGR_TRY(timed(KC_COPY_VIEW, L, st,
+                  [&] { return launch_gen_scatter<T>(const_cast<T*>(src), ws + p.Woff[(size_t)L], nullptr, aL, L,
+                                                     false, st); }),
+            "coarsest gather");
+    for (int k = L - 1; k >= 0; k--) {
+        const GenLevel<T> a = gen_level<T>(p, k);
+        T* z = nullptr;
+        int rc = gen_correction<T>(p, k, src, st, &z);
+        if (rc) return rc;
+        T* Wn = ws + p.Woff[(size_t)k + 1];
+        int64_t vc = 1;
+        for (int d = 0; d < p.nd; d++) vc *= a.mc[d];
+        MGR_TRY(launch_gen_axpy<T>(Wn, z, vc, T(-1), st), "correction launch");
+        T* Wk = (k == 0) ? nullptr : ws + p.Woff[(size_t)k];
+        MGR_TRY(timed(KC_INTERP, k, st, [&] { return launch_gen_interp<T>(src, Wn, dst, Wk, a, k, st); }),
+                "interpolation launch");
+    }
     return MGR_OK;
 }
 
@@ -1088,6 +1478,18 @@ int run(Direction dir, const void* src, void* dst, int dtype, int ndim, const in
     g_err.clear();
     if (!src || !dst) return fail(MGR_ERR_ARG, "src or dst is NULL");
     hipStream_t st = (hipStream_t)stream;
+    if (shape && !dyadic_shape(ndim, shape)) {
+        int rc = validate_general(dtype, ndim, shape, coords, &nlevels);
+        if (rc) return rc;
+        if (dir != DIR_DEC && dir != DIR_REC)
+            return fail(MGR_ERR_SHAPE, "the adjoints take 1- to 3-D grids of 2^k + 1 nodes per dimension");
+        GenPlan* gp = nullptr;
+        rc = get_gen_plan(dtype, ndim, shape, coords, nlevels, st, true, &gp);
+        if (rc) return rc;
+        if (dtype == MGR_F32)
+            return dir == DIR_DEC ? run_gen_decompose<float>(*gp, src, dst, st) : run_gen_recompose<float>(*gp, src, dst, st);
+        return dir == DIR_DEC ? run_gen_decompose<double>(*gp, src, dst, st) : run_gen_recompose<double>(*gp, src, dst, st);
+    }
     Plan* p = nullptr;
     int rc = get_plan(dtype, ndim, shape, coords, nlevels, st, true, &p);
     if (rc) return rc;
@@ -1130,7 +1532,41 @@ struct BatchPlan {
     int n_items = 0, n_tail = 0;
     int chunk = 8, tuned = 0;
     int64_t bytes = 0;             // input bytes of the batch
+    // persistent form (mgr_queue.h): group of each item, dependency group and
+    // size of each group (host copies for the host check), device offsets of
+    // those tables and of the queue words (next, abort, err, done[groups])
+    int persistent = 0;
+    unsigned poll_limit = 1u << 20;
+    double model[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fitted a (ms), x (ms/B), y (ms/item) per launch form
+    std::vector<int> qgrp, qdep, qneed;
+    size_t off_qgrp = 0, off_qdep = 0, off_qneed = 0, off_qwords = 0;
 };
+
+// Groups of the item list for the queue: the items of one field within one
+// wave form a group, which depends on the previous group of the same field.
+void batch_groups(const std::vector<BatchItem>& items, const std::vector<std::pair<int, int>>& waves, int nfields,
+                  std::vector<int>& grp, std::vector<int>& dep, std::vector<int>& need)
+{
+    grp.assign(items.size(), 0);
+    dep.clear();
+    need.clear();
+    std::vector<int> last((size_t)nfields, -1);
+    for (const auto& w : waves) {
+        int cur_field = -1, g = -1;
+        for (int i = w.first; i < w.first + w.second; i++) {
+            const int f = items[(size_t)i].field;
+            if (f != cur_field) {
+                g = (int)need.size();
+                need.push_back(0);
+                dep.push_back(last[(size_t)f]);
+                last[(size_t)f] = g;
+                cur_field = f;
+            }
+            grp[(size_t)i] = g;
+            need[(size_t)g]++;
+        }
+    }
+}
 
 template <typename T>
 struct BatchTables {
@@ -1313,6 +1749,11 @@ int batch_upload(BatchPlan& b, int chunk)
     b.off_tailf = take(sizeof(int) * t.tailf.size());
     b.off_ptrs = take(2 * sizeof(void*) * (size_t)b.nfields);
     b.off_args = take(sizeof(BatchKernelArgs<T>));
+    batch_groups(t.items, t.waves, b.nfields, b.qgrp, b.qdep, b.qneed);
+    b.off_qgrp = take(sizeof(int) * b.qgrp.size());
+    b.off_qdep = take(sizeof(int) * b.qdep.size());
+    b.off_qneed = take(sizeof(int) * b.qneed.size());
+    b.off_qwords = take(sizeof(int) * (3 + b.qneed.size()));
     if (b.dev) (void)hipFree(b.dev);
     b.dev = nullptr;
     hipError_t e = hipMalloc(&b.dev, off);
@@ -1339,7 +1780,10 @@ int batch_upload(BatchPlan& b, int chunk)
                  {b.off_scat, t.scatters.data(), sizeof(BatchScatter<T>) * t.scatters.size()},
                  {b.off_tail, t.tail.data(), sizeof(TailArgs<T>) * t.tail.size()},
                  {b.off_tailf, t.tailf.data(), sizeof(int) * t.tailf.size()},
-                 {b.off_args, &ka, sizeof(ka)}};
+                 {b.off_args, &ka, sizeof(ka)},
+                 {b.off_qgrp, b.qgrp.data(), sizeof(int) * b.qgrp.size()},
+                 {b.off_qdep, b.qdep.data(), sizeof(int) * b.qdep.size()},
+                 {b.off_qneed, b.qneed.data(), sizeof(int) * b.qneed.size()}};
     for (const Part& pt : parts) {
         if (!pt.bytes) continue;
         e = hipMemcpy(d + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice);
@@ -1379,10 +1823,31 @@ int batch_run(BatchPlan& b, const void* const* src, void* const* dst, hipStream_
         MGR_TRY(launch_set_ptrs(c, (void**)(d + b.off_ptrs), st), "batch pointer upload");
     }
     const BatchKernelArgs<T>* dev_args = (const BatchKernelArgs<T>*)(d + b.off_args);
-    for (size_t w = 0; w < b.waves.size(); w++) {
-        const int first = b.waves[w].first, n = b.waves[w].second;
-        MGR_TRY(timed(KC_BATCH, (int)w, st, [&] { return launch_batch_wave<T>(dev_args, first, n, st); }),
-                "batch wave launch");
+    if (b.persistent) {
+        QueueTables qt;
+        qt.grp = (const int*)(d + b.off_qgrp);
+        qt.dep = (const int*)(d + b.off_qdep);
+        qt.need = (const int*)(d + b.off_qneed);
+        qt.total = b.n_items;
+        int* w = (int*)(d + b.off_qwords);
+        QueueState qs;
+        qs.next = w;
+        qs.abort = w + 1;
+        qs.err = w + 2;
+        qs.done = w + 3;
+        const int grid = std::max(1, std::min(b.n_items, batch_queue_slots<T>()));
+        MGR_TRY(timed(KC_BATCH, -1, st,
+                      [&] {
+                          return launch_batch_queue<T>(dev_args, qt, qs, 3 + (int)b.qneed.size(), grid, b.poll_limit,
+                                                       st);
+                      }),
+                "batch queue launch");
+    } else {
+        for (size_t w = 0; w < b.waves.size(); w++) {
+            const int first = b.waves[w].first, n = b.waves[w].second;
+            MGR_TRY(timed(KC_BATCH, (int)w, st, [&] { return launch_batch_wave<T>(dev_args, first, n, st); }),
+                    "batch wave launch");
+        }
     }
     MGR_TRY(timed(KC_TAIL, -1, st,
                   [&] {
@@ -1436,16 +1901,20 @@ int batch_create(int nfields, const int* ndim, const int64_t* const* shapes, con
     return MGR_OK;
 }
 
-// The transaction model of the batch's streaming items (the paper's
-// performance-model pruning of thread-block shapes, Sec. III-C, applied to
-// the chunk of coarse planes per item): bytes moved, with the 3-plane halo of
-// every item, at the streaming kernel's bandwidth, plus a fixed cost per
-// item spread over the device's workgroup slots.
-double batch_model_us(const BatchPlan& b, int chunk)
-{
-    const double bw = 5.0e3;    // bytes per microsecond moved by the streaming kernel
-    const double t_item = 2.0;  // microseconds of start-up and drain per item
+// The transaction model of a batch configuration (the paper's
+// performance-model pruning of launch shapes, Sec. III-C, applied to the
+// streaming items' tile extent along dimension 0, the chunk of coarse
+// planes): predicted time = a + x * bytes + y * items, with bytes the
+// streaming items' traffic including the 3-plane halo each item re-reads
+// and items the streaming items (each with its start-up and drain).  The
+// constants a, x, y are not guessed: batch_autotune fits them, per launch
+// form, to timed runs of the actual fields.
+struct BatchTerms {
     double bytes = 0.0, items = 0.0;
+};
+BatchTerms batch_terms(const BatchPlan& b, int chunk)
+{
+    BatchTerms t;
     const double esz = (b.dtype == MGR_F64) ? 8.0 : 4.0;
     for (int f = 0; f < b.nfields; f++) {
         const Plan& p = *b.plans[(size_t)f];
@@ -1460,12 +1929,51 @@ double batch_model_us(const BatchPlan& b, int chunk)
             const double ch = act0 ? std::min<double>(std::max(chunk, 2), c0) : c0;
             const double nch = act0 ? std::ceil(c0 / ch) : 1.0;
             const double halo = act0 ? (2.0 * ch + 3.0) / (2.0 * ch) : 1.0;
-            bytes += 2.0 * V * esz * halo;
-            items += tiles * nch;
+            t.bytes += 2.0 * V * esz * halo;
+            t.items += tiles * nch;
         }
     }
-    return bytes / bw + t_item * items / (4.0 * device_cu_count());
+    return t;
 }
+
+// Least-squares fit of time = a + x bytes + y items to measured points
+// (normal equations, 3x3, Cramer's rule); negative slopes (noise) are
+// clamped to zero with the intercept refitted.
+void fit_model(const std::vector<BatchTerms>& t, const std::vector<double>& ms, double m[3])
+{
+    double S[3][3] = {{0}}, r[3] = {0};
+    for (size_t i = 0; i < t.size(); i++) {
+        const double v[3] = {1.0, t[i].bytes * 1e-9, t[i].items * 1e-3};  // scaled for conditioning
+        for (int a = 0; a < 3; a++) {
+            r[a] += v[a] * ms[i];
+            for (int c = 0; c < 3; c++) S[a][c] += v[a] * v[c];
+        }
+    }
+    auto det = [](double A[3][3]) {
+        return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    };
+    const double D = det(S);
+    double sol[3] = {0, 0, 0};
+    if (std::fabs(D) > 1e-30) {
+        for (int c = 0; c < 3; c++) {
+            double A[3][3];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) A[i][j] = (j == c) ? r[i] : S[i][j];
+            sol[c] = det(A) / D;
+        }
+    }
+    sol[1] = std::max(0.0, sol[1]);
+    sol[2] = std::max(0.0, sol[2]);
+    double resid = 0.0;
+    for (size_t i = 0; i < t.size(); i++) resid += ms[i] - sol[1] * t[i].bytes * 1e-9 - sol[2] * t[i].items * 1e-3;
+    sol[0] = t.empty() ? 0.0 : resid / (double)t.size();
+    m[0] = sol[0];
+    m[1] = sol[1] * 1e-9;
+    m[2] = sol[2] * 1e-3;
+}
+
+double model_ms(const double m[3], const BatchTerms& t) { return m[0] + m[1] * t.bytes + m[2] * t.items; }
 
 // ---- class-packed layout and progressive recomposition --------------------
 // Segment starts of the class-packed layout: class 0 is the level-0 grid,
@@ -1508,6 +2016,59 @@ int run_pack(bool pack, const void* src, void* dst, int dtype, int ndim, const i
     hipError_t e = (dtype == MGR_F32) ? launch_pack<float>((const float*)src, (float*)dst, a, pack, st)
                                       : launch_pack<double>((const double*)src, (double*)dst, a, pack, st);
     return e == hipSuccess ? MGR_OK : hip_fail(e, "pack launch");
+}
+
+// Quantisation of the classes (in-place or class-packed layout): validated
+// like a refactored array of the problem, bins = one positive finite width
+// per class.
+int run_quant(bool quant, const void* y, int32_t* q, void* out, int dtype, int ndim, const int64_t* shape,
+              int nlevels, int packed, const double* bins, unsigned long long* nclamped, void* stream)
+{
+    if (!q || (quant ? !y : !out)) return fail(MGR_ERR_ARG, "data or code pointer is NULL");
+    if (!bins) return fail(MGR_ERR_ARG, "bins is NULL");
+    if (packed != 0 && packed != 1) return fail(MGR_ERR_ARG, "packed must be 0 or 1");
+    int rc = validate(dtype, ndim, shape, nullptr, &nlevels);
+    if (rc) return rc;
+    if (nlevels > kMaxClassLevels) return fail(MGR_ERR_LEVELS, "too many levels for the class tables");
+    QuantArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const PackArgs pa = pack_args(ndim, shape, nlevels);
+    for (int d = 0; d < 3; d++) a.n[d] = pa.n[d];
+    a.L = nlevels;
+    a.packed = packed;
+    std::memcpy(a.off, pa.off, sizeof(a.off));
+    for (int c = 0; c <= nlevels; c++) {
+        if (!(bins[c] > 0.0) || !std::isfinite(bins[c]))
+            return fail(MGR_ERR_ARG, "bin width of class " + std::to_string(c) + " is not positive and finite");
+        a.bins[c] = bins[c];
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = (dtype == MGR_F32)
+                       ? launch_quant<float>((const float*)y, (int*)q, (float*)out, a, quant, nclamped, st)
+                       : launch_quant<double>((const double*)y, (int*)q, (double*)out, a, quant, nclamped, st);
+    return e == hipSuccess ? MGR_OK : hip_fail(e, "quantisation launch");
+}
+
+// Bin widths for a bound tol on the largest pointwise error of the
+// recomposed field.  The class-0 values enter the recomposition only through
+// interpolation, whose weights are nonnegative and sum to one, so an error e
+// there moves the result by at most max|e|.  A class-l error (l >= 1) enters
+// as its level-l interpolant minus the correction's projection of it onto the
+// coarser space (Eq. (1)), then is interpolated again: at most
+// (1 + |Q|) max|e|, with |Q| the max-norm of the nodal L2 projection onto
+// piecewise-multilinear functions, a tensor product of one-dimensional
+// projections each bounded by 3 on any mesh, so |Q| <= 3^ndim.  Errors of
+// half a bin per class, tol split evenly over the L + 1 classes.
+int quant_bins(int ndim, int nlevels, double tol, double* bins)
+{
+    if (!bins) return fail(MGR_ERR_ARG, "bins is NULL");
+    if (ndim < 1 || ndim > kMaxDim) return fail(MGR_ERR_ARG, "ndim must be 1..3");
+    if (nlevels < 0 || nlevels > kMaxClassLevels) return fail(MGR_ERR_LEVELS, "nlevels out of range");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MGR_ERR_ARG, "tol must be positive and finite");
+    double g = 1.0;  // 3^ndim
+    for (int d = 0; d < ndim; d++) g *= 3.0;
+    for (int c = 0; c <= nlevels; c++) bins[c] = 2.0 * tol / ((double)(nlevels + 1) * (c == 0 ? 1.0 : 1.0 + g));
+    return MGR_OK;
 }
 
 // Recomposition from the classes 0..level: the level grid `level` (stride
@@ -1570,6 +2131,120 @@ int run_recompose_level(const void* src_, void* dst_, int ndim, const int64_t* s
     return run_recompose<T>(*ps, tmp, dst, st);
 }
 
+// The work items, waves and queue groups of a batch, built on the host
+// alone (no device memory: plans keep only their layouts and the pointers in
+// the item arguments are never used), for the host check of the queue.
+template <typename T>
+int batch_host_items_t(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int chunk,
+                       BatchPlan& b)
+{
+    char* const base = reinterpret_cast<char*>((uintptr_t)1 << 40);  // stands in for device allocations
+    size_t ws_total = 0;
+    for (int f = 0; f < nfields; f++) {
+        int nl = nlevels ? nlevels[f] : -1;
+        int rc = validate(b.dtype, ndim[f], shapes[f], nullptr, &nl);
+        if (rc) return fail(rc, "field " + std::to_string(f) + ": " + g_err);
+        if (nl == 0) return fail(MGR_ERR_LEVELS, "field " + std::to_string(f) + ": batches need nlevels >= 1");
+        auto p = std::make_unique<Plan>();
+        plan_dims(*p, 0, b.dtype, ndim[f], shapes[f], nl);
+        std::vector<T> host;
+        plan_layout<T>(*p, nullptr, false, host);
+        p->tables = base;
+        b.kt.push_back(tail_start(*p));
+        b.wsoff.push_back(ws_total);
+        ws_total = align_up(ws_total + p->ws_bytes, 256);
+        b.plans.push_back(std::move(p));
+    }
+    b.ws = base;
+    BatchTables<T> t;
+    int rc = batch_tables<T>(b, chunk, t);
+    b.ws = nullptr;
+    for (auto& p : b.plans) p->tables = nullptr;
+    if (rc) return rc;
+    batch_groups(t.items, t.waves, b.nfields, b.qgrp, b.qdep, b.qneed);
+    b.waves = t.waves;
+    b.n_items = (int)t.items.size();
+    return MGR_OK;
+}
+
+int batch_host_items(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int dtype,
+                     int chunk, BatchPlan& b)
+{
+    if (nfields <= 0 || !ndim || !shapes) return fail(MGR_ERR_ARG, "nfields, ndim or shapes invalid");
+    if (dtype != MGR_F32 && dtype != MGR_F64) return fail(MGR_ERR_ARG, "dtype must be MGR_F32 or MGR_F64");
+    if (chunk < 1 || chunk > kMaxBatchChunk) return fail(MGR_ERR_ARG, "chunk must be 1.." + std::to_string(kMaxBatchChunk));
+    b.dtype = dtype;
+    b.nfields = nfields;
+    return dtype == MGR_F64 ? batch_host_items_t<double>(nfields, ndim, shapes, nlevels, chunk, b)
+                            : batch_host_items_t<float>(nfields, ndim, shapes, nlevels, chunk, b);
+}
+
+// Host side of the queue protocol (mgr_queue.h) for mgr_batch_queue_check.
+struct HostQueueOps {
+    int load_relaxed(int* p) const { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+    void fence_acquire() const { __atomic_thread_fence(__ATOMIC_ACQUIRE); }
+    int fetch_add_relaxed(int* p, int v) const { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+    void add_release(int* p, int v) const { (void)__atomic_fetch_add(p, v, __ATOMIC_RELEASE); }
+    void store_relaxed(int* p, int v) const { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+    void cas_relaxed(int* p, int expect, int v) const
+    {
+        (void)__atomic_compare_exchange_n(p, &expect, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
+    }
+    void pause() const { std::this_thread::yield(); }
+};
+
+// Runs the queue protocol of a plan's item list on nthreads host threads
+// standing in for workgroups; each "runs" an item by checking that its
+// dependency group has finished (a separate sequentially consistent count
+// kept outside the protocol), spinning for a random while, and counting it.
+// The thread that takes stall_item (>= 0) stops there without finishing it,
+// as a workgroup that never completes would.  out: items run, items that
+// started before their dependency group finished, the error word (1 + the
+// item whose wait timed out, or 0), items left untaken.
+int queue_check(const BatchPlan& b, int nthreads, unsigned limit, int stall_item, uint64_t seed, int64_t* out)
+{
+    if (nthreads < 1 || nthreads > 1024) return fail(MGR_ERR_ARG, "nthreads must be 1..1024");
+    const int ng = (int)b.qneed.size();
+    std::vector<int> words((size_t)(3 + ng), 0), fin((size_t)ng, 0);
+    QueueTables qt;
+    qt.grp = b.qgrp.data();
+    qt.dep = b.qdep.data();
+    qt.need = b.qneed.data();
+    qt.total = b.n_items;
+    QueueState qs;
+    qs.next = &words[0];
+    qs.abort = &words[1];
+    qs.err = &words[2];
+    qs.done = &words[3];
+    std::atomic<int64_t> ran{0}, bad{0};
+    auto worker = [&](int tid) {
+        uint64_t x = seed * 0x9E3779B97F4A7C15ull + (uint64_t)tid + 1;
+        for (;;) {
+            const int i = queue_take(qt, qs, limit, HostQueueOps{});
+            if (i < 0) return;
+            const int g = b.qgrp[(size_t)i], dg = b.qdep[(size_t)g];
+            if (dg >= 0 && __atomic_load_n(&fin[(size_t)dg], __ATOMIC_SEQ_CST) != b.qneed[(size_t)dg]) bad++;
+            if (i == stall_item) return;
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            for (volatile unsigned spin = 0; spin < (unsigned)(x % 2000); spin = spin + 1) {
+            }
+            (void)__atomic_fetch_add(&fin[(size_t)g], 1, __ATOMIC_SEQ_CST);
+            ran++;
+            queue_finish(qt, qs, i, HostQueueOps{});
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; t++) th.emplace_back(worker, t);
+    for (auto& t : th) t.join();
+    out[0] = ran.load();
+    out[1] = bad.load();
+    out[2] = words[2];
+    out[3] = std::max<int64_t>(0, (int64_t)b.n_items - (int64_t)words[0]);
+    return MGR_OK;
+}
+
 }  // namespace
 
 
@@ -1582,7 +2257,7 @@ extern "C" {
 int mgr_max_levels(int ndim, const int64_t* shape)
 {
     int nl = -1;
-    int rc = validate(MGR_F32, ndim, shape, nullptr, &nl);
+    int rc = validate_general(MGR_F32, ndim, shape, nullptr, &nl);
     return rc ? -rc : nl;
 }
 
@@ -1639,6 +2314,12 @@ int mgr_prepare(int dtype, int ndim, const int64_t* shape, const double* const* 
 {
     try {
         g_err.clear();
+        if (shape && !dyadic_shape(ndim, shape)) {
+            int rc = validate_general(dtype, ndim, shape, coords, &nlevels);
+            if (rc) return rc;
+            GenPlan* gp = nullptr;
+            return get_gen_plan(dtype, ndim, shape, coords, nlevels, nullptr, false, &gp);
+        }
         Plan* p = nullptr;
         int rc = get_plan(dtype, ndim, shape, coords, nlevels, nullptr, false, &p);
         if (rc) return rc;
@@ -1664,6 +2345,35 @@ int mgr_class_offsets(int ndim, const int64_t* shape, int nlevels, int64_t* offs
     if (rc) return rc;
     class_offsets_of(ndim, shape, nlevels, offsets);
     return MGR_OK;
+}
+
+int mgr_quant_bins(int ndim, int nlevels, double tol, double* bins)
+{
+    g_err.clear();
+    return quant_bins(ndim, nlevels, tol, bins);
+}
+
+int mgr_quantize(const void* src, int32_t* codes, int dtype, int ndim, const int64_t* shape, int nlevels,
+                 int packed, const double* bins, unsigned long long* nclamped, void* stream)
+{
+    try {
+        g_err.clear();
+        return run_quant(true, src, codes, nullptr, dtype, ndim, shape, nlevels, packed, bins, nclamped, stream);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_dequantize(const int32_t* codes, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
+                   int packed, const double* bins, void* stream)
+{
+    try {
+        g_err.clear();
+        return run_quant(false, nullptr, const_cast<int32_t*>(codes), dst, dtype, ndim, shape, nlevels, packed, bins,
+                         nullptr, stream);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
 }
 
 int mgr_pack_classes(const void* src, void* dst, int dtype, int ndim, const int64_t* shape, int nlevels,
@@ -1715,8 +2425,35 @@ int mgr_class_map(int ndim, const int64_t* shape, int nlevels, uint8_t* out)
 {
     g_err.clear();
     if (!out) return fail(MGR_ERR_ARG, "out is NULL");
-    int rc = validate(MGR_F32, ndim, shape, nullptr, &nlevels);
+    int rc = validate_general(MGR_F32, ndim, shape, nullptr, &nlevels);
     if (rc) return rc;
+    if (!dyadic_shape(ndim, shape)) {
+        // a node is on level grid k along d when its index is a multiple of
+        // 2^k or the last one; its class is L - (the finest k <= L whose grid
+        // holds it in every dimension), 0 on the coarsest grid
+        const int L = nlevels;
+        std::vector<std::vector<uint8_t>> lev((size_t)ndim);
+        for (int d = 0; d < ndim; d++) {
+            lev[(size_t)d].resize((size_t)shape[d]);
+            for (int64_t i = 0; i < shape[d]; i++) {
+                int k = 0;
+                while (k < L && (((i >> (k + 1)) << (k + 1)) == i || i == shape[d] - 1)) k++;
+                lev[(size_t)d][(size_t)i] = (uint8_t)k;
+            }
+        }
+        int64_t N = 1;
+        for (int d = 0; d < ndim; d++) N *= shape[d];
+        for (int64_t idx = 0; idx < N; idx++) {
+            int64_t r = idx;
+            int k = L;
+            for (int d = ndim - 1; d >= 0; d--) {
+                k = std::min(k, (int)lev[(size_t)d][(size_t)(r % shape[d])]);
+                r /= shape[d];
+            }
+            out[idx] = (uint8_t)(L - k);
+        }
+        return MGR_OK;
+    }
     int64_t n[3] = {1, 1, 1};
     for (int d = 0; d < ndim; d++) n[3 - ndim + d] = shape[d];
     const int L = nlevels;
@@ -1767,6 +2504,8 @@ void mgr_finalize(void)
         std::lock_guard<std::mutex> lk(g_mu);
         for (auto& kv : g_plans) free_plan(*kv.second);
         g_plans.clear();
+        for (auto& kv : g_gen_plans) free_gen_plan(*kv.second);
+        g_gen_plans.clear();
     }
     std::lock_guard<std::mutex> lk(g_tm_mu);
     for (auto& e : g_tm.ev) {
@@ -1884,41 +2623,74 @@ int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const
         if (!b || !src || !dst) return fail(MGR_ERR_ARG, "plan, src or dst is NULL");
         hipStream_t st = (hipStream_t)stream;
         if (capturing(st)) return fail(MGR_ERR_CAPTURE, "autotuning times launches; not during capture");
-        const int cand[] = {2, 4, 8, 16, 32, 64, 128};
-        std::vector<std::pair<double, int>> ranked;
-        for (int c : cand) ranked.emplace_back(batch_model_us(*b, c), c);
-        std::sort(ranked.begin(), ranked.end());
         if (top_k < 1) top_k = 3;
-        top_k = std::min<int>(top_k, (int)ranked.size());
+        const int cand[] = {2, 4, 8, 16, 32, 64, 128};
+        const int probes[] = {2, 16, 128};
         hipEvent_t e0, e1;
         MGR_TRY(hipEventCreate(&e0), "event");
         MGR_TRY(hipEventCreate(&e1), "event");
-        double best = 1e300;
-        int best_chunk = b->chunk, rc = MGR_OK;
-        for (int i = 0; i < top_k && rc == MGR_OK; i++) {
-            const int c = ranked[(size_t)i].second;
-            rc = b->dtype == MGR_F64 ? batch_upload<double>(*b, c) : batch_upload<float>(*b, c);
-            if (rc) break;
+        int rc = MGR_OK;
+        // median of 3 timed calls after a warm-up, at chunk c
+        auto time_chunk = [&](int c, double* out_ms) -> int {
+            int r = b->dtype == MGR_F64 ? batch_upload<double>(*b, c) : batch_upload<float>(*b, c);
+            if (r) return r;
             std::vector<float> ms;
-            for (int r = 0; r < 4 && rc == MGR_OK; r++) {
+            for (int i = 0; i < 4 && r == MGR_OK; i++) {
                 (void)hipEventRecord(e0, st);
-                rc = mgr_batch_decompose(plan, src, dst, stream);
+                r = mgr_batch_decompose(plan, src, dst, stream);
                 (void)hipEventRecord(e1, st);
                 float t = 0.f;
-                if (rc == MGR_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                if (r == MGR_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
                     ms.push_back(t);
             }
-            if (ms.size() > 1) {
-                std::sort(ms.begin() + 1, ms.end());  // the first run is a warm-up
-                const double med = ms[1 + (ms.size() - 1) / 2];
-                if (med < best) {
-                    best = med;
-                    best_chunk = c;
-                }
+            if (r) return r;
+            if (ms.size() < 2) return fail(MGR_ERR_HIP, "autotune timing failed");
+            std::sort(ms.begin() + 1, ms.end());  // the first run is a warm-up
+            *out_ms = ms[1 + (ms.size() - 1) / 2];
+            return MGR_OK;
+        };
+        double best = 1e300;
+        int best_chunk = b->chunk, best_mode = b->persistent;
+        const unsigned limit = b->poll_limit;
+        // the launch form the plan uses (mgr_batch_set_mode) is tuned
+        for (int mode = b->persistent; mode <= b->persistent && rc == MGR_OK; mode++) {
+            b->persistent = mode;
+            b->poll_limit = limit;
+            // fit the model to three probe configurations, rank every
+            // candidate by it, then time the best top_k
+            std::vector<BatchTerms> terms;
+            std::vector<double> meas;
+            std::map<int, double> timed_ms;
+            for (int c : probes) {
+                double ms = 0.0;
+                rc = time_chunk(c, &ms);
+                if (rc) break;
+                terms.push_back(batch_terms(*b, c));
+                meas.push_back(ms);
+                timed_ms[c] = ms;
             }
+            if (rc) break;
+            fit_model(terms, meas, b->model[mode]);
+            std::vector<std::pair<double, int>> ranked;
+            for (int c : cand) ranked.emplace_back(model_ms(b->model[mode], batch_terms(*b, c)), c);
+            std::sort(ranked.begin(), ranked.end());
+            for (int i = 0; i < std::min<int>(top_k, (int)ranked.size()) && rc == MGR_OK; i++) {
+                const int c = ranked[(size_t)i].second;
+                if (timed_ms.count(c)) continue;
+                double ms = 0.0;
+                rc = time_chunk(c, &ms);
+                if (rc == MGR_OK) timed_ms[c] = ms;
+            }
+            for (const auto& kv : timed_ms)
+                if (kv.second < best) {
+                    best = kv.second;
+                    best_chunk = kv.first;
+                    best_mode = mode;
+                }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        b->persistent = best_mode;
         if (rc) return rc;
         rc = b->dtype == MGR_F64 ? batch_upload<double>(*b, best_chunk) : batch_upload<float>(*b, best_chunk);
         if (rc == MGR_OK) b->tuned = 1;
@@ -1928,12 +2700,25 @@ int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const
     }
 }
 
+int mgr_batch_tuning(const mgr_batch_plan* plan, int* persistent, double* model)
+{
+    const BatchPlan* b = reinterpret_cast<const BatchPlan*>(plan);
+    if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
+    if (persistent) *persistent = b->persistent;
+    if (model)
+        for (int m = 0; m < 2; m++)
+            for (int i = 0; i < 3; i++) model[3 * m + i] = b->model[m][i];
+    return MGR_OK;
+}
+
 int mgr_batch_config(const mgr_batch_plan* plan, int* chunk, int* launches, int64_t* items)
 {
     const BatchPlan* b = reinterpret_cast<const BatchPlan*>(plan);
     if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
     if (chunk) *chunk = b->chunk;
-    if (launches) *launches = (int)b->waves.size() + 1;
+    // kernel launches per call besides the pointer upload: the waves and the
+    // tail, or the queue reset, the queue and the tail
+    if (launches) *launches = b->persistent ? 3 : (int)b->waves.size() + 1;
     if (items) *items = b->n_items;
     return MGR_OK;
 }
@@ -1946,6 +2731,64 @@ int mgr_batch_set_config(mgr_batch_plan* plan, int chunk)
         if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
         if (chunk < 1 || chunk > kMaxBatchChunk) return fail(MGR_ERR_ARG, "chunk must be 1.." + std::to_string(kMaxBatchChunk));
         return b->dtype == MGR_F64 ? batch_upload<double>(*b, chunk) : batch_upload<float>(*b, chunk);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_batch_set_mode(mgr_batch_plan* plan, int persistent, unsigned poll_limit)
+{
+    g_err.clear();
+    BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+    if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
+    if (persistent != 0 && persistent != 1) return fail(MGR_ERR_ARG, "persistent must be 0 or 1");
+    b->persistent = persistent;
+    b->poll_limit = poll_limit ? poll_limit : (1u << 20);
+    return MGR_OK;
+}
+
+int mgr_batch_check(mgr_batch_plan* plan)
+{
+    try {
+        g_err.clear();
+        BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+        if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
+        MGR_TRY(hipDeviceSynchronize(), "synchronise");
+        std::vector<int> w(3 + b->qneed.size(), 0);
+        MGR_TRY(hipMemcpy(w.data(), (char*)b->dev + b->off_qwords, sizeof(int) * w.size(), hipMemcpyDeviceToHost),
+                "read queue words");
+        if (w[1] || w[2]) {
+            std::string d;
+            const int item = w[2] - 1;
+            if (item >= 0 && item < b->n_items) {
+                const int g = b->qgrp[(size_t)item], dg = b->qdep[(size_t)g];
+                d = " (group " + std::to_string(g) + ", waiting on group " + std::to_string(dg);
+                if (dg >= 0)
+                    d += " with " + std::to_string(w[3 + (size_t)dg]) + " of " + std::to_string(b->qneed[(size_t)dg]) +
+                         " items finished";
+                d += "; " + std::to_string(w[0]) + " of " + std::to_string(b->n_items) + " items taken)";
+            }
+            return fail(MGR_ERR_HIP, "persistent batch: a dependency wait timed out at work item " +
+                                         std::to_string(item) + d + "; the outputs of that run are incomplete");
+        }
+        return MGR_OK;
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_batch_queue_check(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int dtype,
+                          int chunk, int nthreads, unsigned poll_limit, int stall_item, uint64_t seed, int64_t* out)
+{
+    try {
+        g_err.clear();
+        if (!out) return fail(MGR_ERR_ARG, "out is NULL");
+        BatchPlan b;
+        int rc = batch_host_items(nfields, ndim, shapes, nlevels, dtype, chunk, b);
+        if (rc) return rc;
+        return queue_check(b, nthreads, poll_limit ? poll_limit : (1u << 20), stall_item, seed, out);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
     } catch (...) {
         return fail(MGR_ERR_HIP, "unexpected exception");
     }

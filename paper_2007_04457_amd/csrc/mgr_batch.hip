@@ -152,6 +152,80 @@ k_batch(const BatchKernelArgs<T>* __restrict__ A, int first)
     }
 }
 
+// Device side of the queue protocol (mgr_queue.h): agent-scope atomics on
+// the plan's queue words; polls sleep between loads.
+struct DevQueueOps {
+    __device__ int load_relaxed(int* p) const { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ void fence_acquire() const { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+    __device__ int fetch_add_relaxed(int* p, int v) const
+    {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // release at agent scope (one write-back of this XCD's L2), waited for
+    // explicitly before the counter moves
+    __device__ void add_release(int* p, int v) const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+        (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ void store_relaxed(int* p, int v) const
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ void cas_relaxed(int* p, int expect, int v) const
+    {
+        (void)__hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ void pause() const { __builtin_amdgcn_s_sleep(2); }
+};
+
+template <typename T>
+__device__ __forceinline__ void run_item(const BatchKernelArgs<T>* A, const BatchItem* itp)
+{
+    switch (itp->type) {
+        case BI_STREAM3: exec_stream<T, true, true>(A, itp); break;
+        case BI_STREAM2: exec_stream<T, true, false>(A, itp); break;
+        case BI_STREAM1: exec_stream<T, false, false>(A, itp); break;
+        case BI_ROWS: exec_rows<T>(A, itp); break;
+        case BI_STRIDED: exec_strided<T>(A, itp); break;
+        case BI_SCATTER: exec_scatter<T>(A, itp); break;
+        default: exec_phase<T>(A, itp); break;
+    }
+}
+
+// The persistent form: every workgroup takes items from the queue until it
+// is empty (or the run is aborted), waiting for each item's dependency
+// group first.  The grid size is free (a workgroup takes an item only while
+// it runs).  After an item every thread waits until its own memory
+// operations have completed (so its stores are in the L2), the barrier then
+// lets thread 0 release them at agent scope with one write-back of the L2
+// before it marks the item finished; thread 0's acquire after the wait
+// precedes the barrier that starts the next item for every thread.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_batch_queue(const BatchKernelArgs<T>* __restrict__ A, QueueTables qt, QueueState qs, unsigned limit)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = queue_take(qt, qs, limit, DevQueueOps{});
+        __syncthreads();
+        const int i = s_item;
+        if (i < 0) return;
+        run_item(A, A->items + i);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no memory operation moves below the wait
+        __builtin_amdgcn_s_waitcnt(0);             // this wave's loads and stores completed
+        __syncthreads();
+        if (threadIdx.x == 0) queue_finish(qt, qs, i, DevQueueOps{});
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero_words(int* p, int n)
+{
+    for (int i = (int)(blockIdx.x * 256 + threadIdx.x); i < n; i += (int)(gridDim.x * 256)) p[i] = 0;
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -192,6 +266,44 @@ hipError_t launch_set_ptrs(const PtrChunk& c, void** dst, hipStream_t st)
     return hipGetLastError();
 }
 
+// The whole queue in one launch of `grid` workgroups, after zeroing the
+// queue words (`words` ints from qs.next: next, abort, err, then done[]).
+template <typename T>
+hipError_t launch_batch_queue(const BatchKernelArgs<T>* dev_a, const QueueTables& qt, const QueueState& qs, int words,
+                              int grid, unsigned limit, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min(64, (words + 255) / 256)), dim3(256), 0, st, qs.next,
+                       words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_queue<T>, dim3((unsigned)grid), dim3(kThreads), sizeof(BatchSmem<T>), st, dev_a, qt, qs,
+                       limit);
+    return hipGetLastError();
+}
+
+// Workgroups of the queue kernel that the device holds at once.
+template <typename T>
+int batch_queue_slots()
+{
+    static int cache[2] = {0, 0};
+    int& c = cache[sizeof(T) == 8 ? 1 : 0];
+    if (c == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_queue<T>, kThreads, sizeof(BatchSmem<T>)) !=
+                hipSuccess ||
+            n <= 0)
+            n = 1;
+        c = n * device_cu_count();
+    }
+    return c;
+}
+
+template hipError_t launch_batch_queue<float>(const BatchKernelArgs<float>*, const QueueTables&, const QueueState&, int,
+                                              int, unsigned, hipStream_t);
+template hipError_t launch_batch_queue<double>(const BatchKernelArgs<double>*, const QueueTables&, const QueueState&,
+                                               int, int, unsigned, hipStream_t);
+template int batch_queue_slots<float>();
+template int batch_queue_slots<double>();
 template hipError_t launch_batch_wave<float>(const BatchKernelArgs<float>*, int, int, hipStream_t);
 template hipError_t launch_batch_wave<double>(const BatchKernelArgs<double>*, int, int, hipStream_t);
 

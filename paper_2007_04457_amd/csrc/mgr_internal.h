@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "mgr_queue.h"
+
 namespace mgr {
 
 // Strided 3-D view: element (j0, j1, j2) lives at j0*s[0] + j1*s[1] + j2*s[2].
@@ -186,6 +188,22 @@ __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uns
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// The same with a wave-uniform byte offset `so` added to the address (the
+// instruction's scalar-offset field): one descriptor can then serve every row
+// of a plane, the row's offset in a scalar register.  Masking by range works
+// as above through the per-lane offset.
+template <typename T>
+__device__ __forceinline__ T buf_load_so(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned so);
+template <>
+__device__ __forceinline__ float buf_load_so<float>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned so)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, __builtin_amdgcn_readfirstlane((int)so), 0));
+}
+template <>
+__device__ __forceinline__ double buf_load_so<double>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned so)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, __builtin_amdgcn_readfirstlane((int)so), 0));
+}
 // (All overloads of buf_store live here together: an overload declared in a
 // nested namespace would hide these from code inside it.)
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
@@ -196,6 +214,16 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store_so(float v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned so)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off,
+                                          __builtin_amdgcn_readfirstlane((int)so), 0);
+}
+__device__ __forceinline__ void buf_store_so(double v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned so)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, __builtin_amdgcn_readfirstlane((int)so),
+                                          0);
 }
 // Non-temporal stores (cache policy bit 1, "nt"): for whole-line output that
 // nothing in the call reads again.  Keeping such a stream out of the caches
@@ -299,6 +327,13 @@ hipError_t launch_set_ptrs(const PtrChunk& c, void** dst, hipStream_t st);
 // Runs items [first, first + n) of the table dev_a->items, one workgroup each.
 template <typename T>
 hipError_t launch_batch_wave(const BatchKernelArgs<T>* dev_a, int first, int n, hipStream_t st);
+// Persistent form: all items in one launch of `grid` workgroups through the
+// queue of mgr_queue.h (the queue words zeroed first by a small kernel).
+template <typename T>
+hipError_t launch_batch_queue(const BatchKernelArgs<T>* dev_a, const QueueTables& qt, const QueueState& qs, int words,
+                              int grid, unsigned limit, hipStream_t st);
+template <typename T>
+int batch_queue_slots();
 int device_cu_count();
 
 // Kernel classes (for timing and profiling names).
@@ -340,5 +375,62 @@ struct PackArgs {
 template <typename T>
 hipError_t launch_pack(const T* src, T* dst, const PackArgs& a, bool pack, hipStream_t st);
 
+// Quantisation of the classes (mgr_quant.hip): internal 3-D sizes, level
+// count, layout, class segment starts (class-packed layout) and the bin width
+// of every class.  seg / nseg are filled in by the launcher.
+struct QuantArgs {
+    int64_t n[3];
+    int L;
+    int packed;
+    int64_t seg, nseg;
+    int64_t off[kMaxClassLevels + 2];
+    double bins[kMaxClassLevels + 1];
+};
+// quant: codes q <- y; else out <- dequantised q.  counter (device, may be
+// null) receives the number of clamped codes.
+template <typename T>
+hipError_t launch_quant(const T* y, int* q, T* out, QuantArgs a, bool quant, unsigned long long* counter,
+                        hipStream_t st);
+
+
+// ---- general tensor grids (mgr_general.hip) ---------------------------------
+// 1..4 dimensions of any size >= 3; level grids keep the multiples of 2^k and
+// the last node along each dimension.
+constexpr int kGenMaxDim = 4;
+// One level step: full-array sizes and strides, level-grid and coarse sizes,
+// and per dimension the interpolation weight pairs of the level grid's
+// fine-only nodes (wl lower, wh upper neighbour, indexed by level index) and
+// the load-vector rows K (5 per coarse node, fine nodes f(i) - 2 .. f(i) + 2).
+template <typename T>
+struct GenLevel {
+    int nd;
+    int64_t n[kGenMaxDim], st[kGenMaxDim];
+    int64_t m[kGenMaxDim], mc[kGenMaxDim];
+    const T* wl[kGenMaxDim];
+    const T* wh[kGenMaxDim];
+    const T* K[kGenMaxDim];
+};
+// One load-vector pass along dimension d: input and output box sizes; full:
+// read the input from the full array (the level grid's coefficients).
+struct GenPass {
+    int d, full;
+    int64_t in[kGenMaxDim], out[kGenMaxDim];
+};
+template <typename T>
+hipError_t launch_gen_coef(const T* src, const T* Wk, T* dst, T* Wn, const GenLevel<T>& a, int k, hipStream_t st);
+template <typename T>
+hipError_t launch_gen_masstrans(const T* in, const T* y, T* out, const GenLevel<T>& a, const GenPass& p, int k,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_gen_axpy(T* W, const T* Z, int64_t n, T sign, hipStream_t st);
+template <typename T>
+hipError_t launch_gen_interp(const T* y, const T* Wn, T* dst, T* Wk, const GenLevel<T>& a, int k, hipStream_t st);
+template <typename T>
+hipError_t launch_gen_scatter(T* full, T* W, const T* Z, const GenLevel<T>& a, int k, bool to_full, hipStream_t st);
+// Partitioned solve of every fibre of length n along the middle index of a
+// packed (outer, n, inner) box, in place; Yb as for launch_solve_partitioned.
+template <typename T>
+hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, SolveTables<T> tb, T* Yb,
+                               hipStream_t st);
 
 }  // namespace mgr

@@ -158,12 +158,20 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
 template <typename T>
 hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st)
 {
+    int64_t inner = 1, outer = 1;
+    for (int e = d + 1; e < 3; e++) inner *= fv.n[e];
+    for (int e = 0; e < d; e++) outer *= fv.n[e];
+    return launch_solve_fibres<T>(F, fv.n[d], inner, outer, tb, Yb, st);
+}
+
+template <typename T>
+hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, SolveTables<T> tb, T* Yb,
+                               hipStream_t st)
+{
     FibreMap m;
-    m.n = fv.n[d];
-    m.inner = 1;
-    for (int e = d + 1; e < 3; e++) m.inner *= fv.n[e];
-    m.outer = 1;
-    for (int e = 0; e < d; e++) m.outer *= fv.n[e];
+    m.n = n;
+    m.inner = inner;
+    m.outer = outer;
     m.nfib = m.inner * m.outer;
     m.S = tb.S;
     if (m.inner == 1 && m.S <= kBlk && m.n <= rows_span<T>()) {
@@ -250,6 +258,10 @@ template bool solve_small_fits<double>(View3, const int*, int, const SolveTables
 template hipError_t launch_solve_small<float>(float*, View3, const int*, int, const SolveTables<float>*, hipStream_t);
 template hipError_t launch_solve_small<double>(double*, View3, const int*, int, const SolveTables<double>*,
                                                hipStream_t);
+template hipError_t launch_solve_fibres<float>(float*, int64_t, int64_t, int64_t, SolveTables<float>, float*,
+                                               hipStream_t);
+template hipError_t launch_solve_fibres<double>(double*, int64_t, int64_t, int64_t, SolveTables<double>, double*,
+                                                hipStream_t);
 template hipError_t launch_solve_partitioned<float>(float*, View3, int, SolveTables<float>, float*,
                                                     hipStream_t);
 template hipError_t launch_solve_partitioned<double>(double*, View3, int, SolveTables<double>, double*,

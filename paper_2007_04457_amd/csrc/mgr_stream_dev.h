@@ -86,39 +86,42 @@ constexpr int stream_min_waves()
     return stream_ring<T, kDec, kZ>() == 4 ? 5 : 1;
 }
 
-// A lane's CPL consecutive columns of one row.  FP32 pairs move as one
-// 8-byte access where the columns are adjacent in memory (kU), else as two
-// 4-byte accesses `step` bytes apart.  The hardware range check is per
-// dword, so a pair that straddles the end of a row keeps its first element.
+// A lane's CPL consecutive columns of one row: the row at scalar byte offset
+// `so` from the descriptor's base.  FP32 pairs move as one 8-byte access
+// where the columns are adjacent in memory (kU), else as two 4-byte accesses
+// `step` bytes apart.  The hardware range check is per dword, so a pair that
+// straddles the end of the range keeps its first element.
 template <bool kU, typename T, int N>
-__device__ __forceinline__ void buf_load_cols(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned step, T (&v)[N])
+__device__ __forceinline__ void buf_load_cols(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned so, unsigned step,
+                                              T (&v)[N])
 {
     static_assert(N == 1 || (N == 2 && sizeof(T) == 4), "one column, or an FP32 pair");
     if constexpr (N == 1) {
-        v[0] = buf_load<T>(r, off);
+        v[0] = buf_load_so<T>(r, off, so);
     } else if (kU) {
-        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, __builtin_amdgcn_readfirstlane((int)so), 0);
         v[0] = __builtin_bit_cast(T, w.x);
         v[1] = __builtin_bit_cast(T, w.y);
     } else {
-        v[0] = buf_load<T>(r, off);
-        v[1] = buf_load<T>(r, off + step);
+        v[0] = buf_load_so<T>(r, off, so);
+        v[1] = buf_load_so<T>(r, off + step, so);
     }
 }
 template <bool kU, typename T, int N>
-__device__ __forceinline__ void buf_store_cols(const T (&v)[N], __amdgpu_buffer_rsrc_t r, unsigned off, unsigned step)
+__device__ __forceinline__ void buf_store_cols(const T (&v)[N], __amdgpu_buffer_rsrc_t r, unsigned off, unsigned so,
+                                               unsigned step)
 {
     static_assert(N == 1 || (N == 2 && sizeof(T) == 4), "one column, or an FP32 pair");
     if constexpr (N == 1) {
-        buf_store(v[0], r, off);
+        buf_store_so(v[0], r, off, so);
     } else if (kU) {
         u32x2 w;
         w.x = __builtin_bit_cast(unsigned, v[0]);
         w.y = __builtin_bit_cast(unsigned, v[1]);
-        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, __builtin_amdgcn_readfirstlane((int)so), 0);
     } else {
-        buf_store(v[0], r, off);
-        buf_store(v[1], r, off + step);
+        buf_store_so(v[0], r, off, so);
+        buf_store_so(v[1], r, off + step, so);
     }
 }
 
@@ -240,14 +243,18 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     const T* const sUrow = sU + rg * NCW;
     T* const sCrow = sC + rg * H;
     const int oR0 = kAct1 ? 2 * I1 : 0, oR1 = kAct1 ? min(2 * (I1 + kT1), m1) : 1;
-    // A row's buffer descriptor starts at the row (wave-uniform, scalar) and
-    // holds the row's bytes, or none for a row outside the grid (or not owned,
-    // for the outputs)
-    const unsigned rowA = (unsigned)((m2 - 1) * as2 + 1) * S;
-    const unsigned rowC = (unsigned)((m2 - 1) * cs2 + 1) * S;
-    const unsigned rowW = (unsigned)(((m2 - 1) / 2) * ws2 + 1) * S;
+    // One buffer descriptor per array and plane, holding the plane's bytes;
+    // each row is reached through the instruction's scalar offset (the row's
+    // byte offset in the plane, kept in a scalar register for the whole
+    // kernel).  A row outside the grid loads the nearest grid row instead and
+    // its values are replaced by zero where they are used (rin), so the
+    // loads stay unconditional and need no per-row lane offsets.
+    const unsigned spanA = (unsigned)((m1 - 1) * as1 + (m2 - 1) * as2 + 1) * S;
+    const unsigned spanC = (unsigned)((m1 - 1) * cs1 + (m2 - 1) * cs2 + 1) * S;
+    const unsigned spanW = (unsigned)(((m1 - 1) / 2) * ws1 + ((m2 - 1) / 2) * ws2 + 1) * S;
     int gr[NRW];               // grid row (uniform)
     bool rin[NRW], rown[NRW];  // in the grid / owned (uniform)
+    unsigned soA[NRW], soC[NRW], soW[NRW];  // row byte offsets in a plane (uniform)
     T wrl[NRW], wrh[NRW];
 #pragma unroll
     for (int k = 0; k < NRW; k++) {
@@ -255,6 +262,10 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
         gr[k] = R0 + r;
         rin[k] = r < NR && gr[k] >= 0 && gr[k] < m1;
         rown[k] = rin[k] && gr[k] >= oR0 && gr[k] < oR1;
+        const int grc = min(max(gr[k], 0), m1 - 1);
+        soA[k] = (unsigned)uni((int)((unsigned)(grc * as1) * S));
+        soC[k] = (unsigned)uni((int)((unsigned)(grc * cs1) * S));
+        soW[k] = (unsigned)uni((int)((unsigned)((grc >> 1) * ws1) * S));
         wrl[k] = T(0);
         wrh[k] = T(0);
         if (kDec && rin[k]) {
@@ -302,11 +313,12 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     using Cols = T[CPL];
     auto load_plane = [&](int f, Cols (&v)[NRW], Cols (&vz)[NRW]) {
         const int64_t po = mul64(f, as0);
+        const __amdgpu_buffer_rsrc_t rA = make_rsrc(a.A + po, spanA);
+        const __amdgpu_buffer_rsrc_t rZ = make_rsrc(kZ ? a.Z + po : a.A, kZ ? spanA : 0u);
 #pragma unroll
         for (int k = 0; k < NRW; k++) {
-            const int64_t o = po + (int64_t)gr[k] * as1;
-            buf_load_cols<kU>(make_rsrc(a.A + o, rin[k] ? rowA : 0u), cA, stepA, v[k]);
-            if (kZ) buf_load_cols<kU>(make_rsrc(a.Z + o, rin[k] ? rowA : 0u), cA, stepA, vz[k]);
+            buf_load_cols<kU>(rA, cA, soA[k], stepA, v[k]);
+            if (kZ) buf_load_cols<kU>(rZ, cA, soA[k], stepA, vz[k]);
         }
     };
 
@@ -325,6 +337,7 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     };
     // Coefficients of plane f into sC (and C, W); returns through P the 2-D
     // interpolant of an even plane.  Ends with a barrier after the sC writes.
+    // The caller has replaced the values of rows outside the grid by zero.
     auto coef_plane = [&](int f, bool even, const Cols (&cur)[NRW], Cols (&P)[NRW], const Cols (&Pa)[NRW],
                           const Cols (&Pb)[NRW]) {
         if (!kDec) {
@@ -343,11 +356,11 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
         }
         const bool fown = f >= oF0 && f < oF1;
         const int64_t pc = mul64(f, cs0);
-        auto rC = [&](int k) { return make_rsrc(a.C + pc + (int64_t)gr[k] * cs1, rowC); };
+        const __amdgpu_buffer_rsrc_t rC = make_rsrc(a.C + pc, spanC);
         Cols cv[NRW];
         if (even) {
             const int64_t pw = mul64(f >> 1, ws0);
-            auto rW = [&](int k) { return make_rsrc(a.W + pw + (int64_t)(gr[k] >> 1) * ws1, rowW); };
+            const __amdgpu_buffer_rsrc_t rW = make_rsrc(a.W + pw, spanW);
 #pragma unroll
             for (int k = 0; k < NRW; k++) {
                 if (!row_exists(k)) continue;
@@ -388,8 +401,8 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
                     cv[k][j] = (!RP && ce) ? cur[k][j] : c;
                 }
                 if (fown && rown[k]) {
-                    buf_store_cols<kU>(cv[k], rC(k), cC, stepC);
-                    if (!RP) buf_store(cur[k][jw], rW(k), cW);
+                    buf_store_cols<kU>(cv[k], rC, cC, soC[k], stepC);
+                    if (!RP) buf_store_so(cur[k][jw], rW, cW, soW[k]);
                 }
             }
         } else {
@@ -404,7 +417,7 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
                     cv[k][j] = cur[k][j] - lerp2(wl, Pa[k][j], wh, Pb[k][j]);
                     sC_at(k, j) = cv[k][j];
                 }
-                if (fown && rown[k]) buf_store_cols<kU>(cv[k], rC(k), cC, stepC);
+                if (fown && rown[k]) buf_store_cols<kU>(cv[k], rC, cC, soC[k], stepC);
             }
         }
         lds_barrier();
@@ -468,7 +481,7 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
 #pragma unroll
         for (int k = 0; k < NRW; k++)
 #pragma unroll
-            for (int j = 0; j < CPL; j++) cur[k][j] = kZ ? B0[k][j] + Z0[k][j] : B0[k][j];
+            for (int j = 0; j < CPL; j++) cur[k][j] = rin[k] ? (kZ ? B0[k][j] + Z0[k][j] : B0[k][j]) : T(0);
         coef_plane(0, true, cur, Pn, Pp, Pp);
         reduce_plane(g);
         store_f(0, g, true);
@@ -493,6 +506,13 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
 #pragma unroll
     for (int q = 0; q < NOUT; q++) accA[q] = accB[q] = accC[q] = T(0);
     const T* const k0 = sK0 + 5 * (F0 / 2 - P0 + 1) + 2;  // k0[5 (i - F0/2) + t]
+    // rows outside the grid (they loaded the nearest grid row) read as zero
+    auto mask_rows = [&](Cols (&B)[NRW]) {
+#pragma unroll
+        for (int q = 0; q < NRW; q++)
+#pragma unroll
+            for (int jj = 0; jj < CPL; jj++) B[q][jj] = rin[q] ? B[q][jj] : T(0);
+    };
     auto consume = [&](int j, Cols (&B)[NRW], Cols (&BZ)[NRW]) {
         const int f = seq(j);
         const bool even = (j & 1) || j == 0;
@@ -500,10 +520,11 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
 #pragma unroll
             for (int q = 0; q < NRW; q++)
 #pragma unroll
-                for (int jj = 0; jj < CPL; jj++) cur[q][jj] = B[q][jj] + BZ[q][jj];
+                for (int jj = 0; jj < CPL; jj++) cur[q][jj] = rin[q] ? B[q][jj] + BZ[q][jj] : T(0);
             load_plane(seq(j + D), B, BZ);
             coef_plane(f, even, cur, Pn, Pp, Pn);
         } else {
+            mask_rows(B);
             coef_plane(f, even, B, Pn, Pp, Pn);
             load_plane(seq(j + D), B, BZ);
         }

@@ -44,8 +44,19 @@ def test_max_levels(lib):
     assert lib.mgr_max_levels(2, _lib.shape_arg((8193, 8193))) == 12
     assert lib.mgr_max_levels(3, _lib.shape_arg((1025, 1025, 257))) == 7
     assert lib.mgr_max_levels(3, _lib.shape_arg((65, 65, 65))) == 5
-    assert lib.mgr_max_levels(2, _lib.shape_arg((10, 9))) == -2
-    assert lib.mgr_max_levels(4, _lib.shape_arg((9, 9, 9, 9))) == -1
+    # any size >= 3 and up to four dimensions (nested grids keep the last
+    # node): the oracle's count
+    for shape in [(10, 9), (9, 9, 9, 9), (3, 100), (6, 7, 12, 5), (1000,), (33, 20, 513)]:
+        assert lib.mgr_max_levels(len(shape), _lib.shape_arg(shape)) == oracle.max_levels(shape), shape
+    assert lib.mgr_max_levels(2, _lib.shape_arg((2, 9))) == -2
+    assert lib.mgr_max_levels(5, _lib.shape_arg((9, 9, 9, 9, 9))) == -1
+
+
+@pytest.mark.parametrize("shape,L", [((10, 9), -1), ((6, 7, 12, 5), -1), ((6, 7, 12, 5), 1), ((100,), 3),
+                                     ((5, 17, 9, 9), -1), ((20, 3, 13), 1)])
+def test_class_map_general_shapes_matches_oracle(lib, shape, L):
+    from paper_2007_04457_amd import mgr_class_map
+    assert np.array_equal(mgr_class_map(shape, L), oracle.class_map(shape, L))
 
 
 @pytest.mark.parametrize("shape,L", [((17, 9, 33), -1), ((17, 9, 33), 3), ((65,), 2), ((9, 17), 1)])
@@ -62,12 +73,20 @@ def _call(lib, fn, shape, nlevels=-1, coords=None, dtype=0, ptr=16):
 @pytest.mark.parametrize("fn", ["mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint"])
 def test_validation_errors_before_any_device_work(lib, fn):
     # validation happens before any HIP call, so these run without a GPU
-    assert _call(lib, fn, (10, 9)) == 2
+    general = fn in ("mgr_decompose", "mgr_recompose")  # any size >= 3, up to 4-D
+    if general:
+        # accepted; the call then needs a device (here: a HIP status)
+        assert _call(lib, fn, (10, 9)) not in (1, 2, 3, 4)
+        assert _call(lib, fn, (9, 9, 9, 9)) not in (1, 2, 3, 4)
+        assert _call(lib, fn, (10, 9), nlevels=4) == 3
+    else:
+        assert _call(lib, fn, (10, 9)) == 2
+        assert _call(lib, fn, (9, 9, 9, 9)) == 2
+    assert _call(lib, fn, (9, 9, 9, 9, 9)) == 1
     assert _call(lib, fn, (2, 9)) == 2
     assert _call(lib, fn, (9, 9), nlevels=4) == 3
     assert _call(lib, fn, (9, 9), nlevels=-2) == 3
     assert _call(lib, fn, (9, 9), dtype=7) == 1
-    assert _call(lib, fn, (9, 9, 9, 9)) == 1
     bad = [np.array([0, 1, 2, 3, 3, 5, 6, 7, 8.0]), None]
     assert _call(lib, fn, (9, 9), coords=bad) == 4
     nan = [np.array([0, 1, 2, np.nan, 4, 5, 6, 7, 8.0]), None]
@@ -142,3 +161,34 @@ def test_packed_and_progressive_validation(lib):
     assert lib.mgr_recompose_level(16, 16, 0, 2, shp, None, -1, 1, 0, None) == 1   # in place
     off = (ctypes.c_int64 * 4)()
     assert lib.mgr_class_offsets(2, shp, -1, off) == 0 and list(off) == [0, 9, 25, 81]
+
+
+@pytest.mark.parametrize("ndim,L,tol", [(1, 5, 1e-3), (2, 12, 0.25), (3, 8, 1e-6), (3, 0, 2.0)])
+def test_quant_bins_match_the_oracle(lib, ndim, L, tol):
+    """The library's bin widths for a max-norm bound are the oracle's closed
+    form, bit for bit (host code; both write b_0 = 2 tol / (L + 1) and
+    b_c = 2 tol / ((L + 1)(1 + 3^ndim)))."""
+    assert np.array_equal(mgr.quant_bins(ndim, L, tol), oracle.quant_bins(ndim, L, tol))
+
+
+def test_quant_argument_errors(lib):
+    """Validation of the quantisation entry points happens on the host,
+    before anything is enqueued (no kernel runs here)."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    shape = (17, 9)
+    bins = np.ones(4, dtype=np.float64)
+    bad = bins.copy()
+    bad[2] = 0.0
+    call = lambda b, L=3, packed=0, codes=16: lib.mgr_quantize(16, codes, 0, 2, _lib.shape_arg(shape), L, packed,
+                                                               b.ctypes.data_as(dp) if b is not None else None,
+                                                               None, None)
+    assert call(None) == 1
+    assert call(bad) == 1
+    assert call(bins, codes=None) == 1
+    assert call(bins, packed=2) == 1
+    assert call(bins, L=9) == 3
+    assert lib.mgr_quantize(16, 16, 0, 2, _lib.shape_arg((10, 9)), 3, 0, bins.ctypes.data_as(dp), None, None) == 2
+    assert lib.mgr_dequantize(16, None, 0, 2, _lib.shape_arg(shape), 3, 0, bins.ctypes.data_as(dp), None) == 1
+    out = np.zeros(4)
+    assert lib.mgr_quant_bins(2, 3, -1.0, out.ctypes.data_as(dp)) == 1
+    assert lib.mgr_quant_bins(4, 3, 1.0, out.ctypes.data_as(dp)) == 1

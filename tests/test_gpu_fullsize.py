@@ -181,5 +181,12 @@ def test_full_size_recompose_adjoint_257_blobs():
     want = oracle.recompose_adjoint(gd)
     a = mgr.recompose_adjoint(g.to(DEV))
     torch.cuda.synchronize()
-    err = rel_err(a.double().cpu().numpy(), want, np.max(np.abs(gd)))
+    # per class, against the size of what the class's step computes with:
+    # the classes of R^T g span 0.4 (finest) to 5.8e4 (coarsest) times
+    # max|g| here, so float32 rounding of the coarsest outputs alone is
+    # ~2e-3 of max|g| (see step_scaled_err)
+    from test_gpu_parity import step_scaled_err
+    prev = oracle.set_threads(8)  # the oracle's output does not depend on it
+    err = step_scaled_err(a.double().cpu().numpy(), want, gd, None, oracle.max_levels(shape))
+    oracle.set_threads(prev)
     assert err <= TOL[torch.float32], err
