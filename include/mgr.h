@@ -228,6 +228,16 @@ void mgr_finalize(void);
  * previous value.  Process-wide; affects calls enqueued afterwards. */
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes);
 
+/* Workgroup slots per compute unit that the recomposition's finest-level
+ * correction leaves free.  The recomposition computes the finest level
+ * step's correction on one stream while the coarser level steps run on
+ * others; the finest correction's launches are sized to the device's
+ * resident capacity, and without free slots every small launch of the
+ * coarser levels waits for its workgroups to finish.  Clamped to 0..8;
+ * default 2.  Returns the previous value.  Process-wide; affects calls
+ * enqueued afterwards; results do not depend on it. */
+int mgr_set_recompose_reserve(int slots);
+
 /* ---- batched decomposition ----------------------------------------------
  * Many independent fields (any mix of shapes, dimensionalities, coordinates
  * and level counts, one dtype) decomposed together: every workgroup-sized

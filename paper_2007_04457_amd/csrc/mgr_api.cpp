@@ -659,7 +659,7 @@ T* corr(const Plan& p, int k, void* ws = nullptr)
 // vector goes to corr(k).
 template <typename T>
 int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 av, T* C, View3 cv,
-                 T* W, bool write_coarse, hipStream_t st, T* Fout = nullptr)
+                 T* W, bool write_coarse, hipStream_t st, T* Fout = nullptr, int reserve = 0)
 {
     const LevelLayout& ly = p.lv[(size_t)k];
     StreamArgs<T> a;
@@ -676,14 +676,14 @@ int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 a
     a.write_coarse = write_coarse ? 1 : 0;
     a.chunk = a.nt1 = a.nt2 = a.nch = 0;
     MGR_TRY(timed(dec ? KC_STREAM_DEC : KC_STREAM_LOAD, k, st,
-                  [&] { return launch_stream_level<T>(a, dec, st); }),
+                  [&] { return launch_stream_level<T>(a, dec, st, reserve); }),
             "level kernel launch");
     return MGR_OK;
 }
 
 // Correction solves of level step k on F along every dimension, in place.
 template <typename T>
-int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = nullptr)
+int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = nullptr, int reserve = 0)
 {
     T* ws = (T*)p.ws;
     View3 fv = packed(p.lv[(size_t)k].mc);
@@ -708,7 +708,7 @@ int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = 
         if (!p.active[d]) continue;
         SolveTables<T> tb = solve_tables_of<T>(p, k, d);
         MGR_TRY(timed(KC_SOLVE, k, st,
-                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, Yb ? Yb : ws + p.Yb, st); }),
+                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, Yb ? Yb : ws + p.Yb, st, reserve); }),
                 "solve launch");
     }
     return MGR_OK;
@@ -902,13 +902,21 @@ bool aux_ready()
     return g_aux[dev].s != nullptr;
 }
 
+// Workgroup slots per CU that the recomposition's finest correction (sized
+// to the resident capacity) leaves free for the coarse levels running
+// alongside it (mgr_set_recompose_reserve).
+std::atomic<int> g_rec_reserve{2};
+
 // Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
 // The correction z_k of every level step depends on the stored coefficients
 // alone (its load vector is formed from them), so they are computed on two
 // more streams (the finest level step on one, the coarser ones, coarsest
 // first, on the other) while the caller's stream runs the coarsest levels
 // and the interpolations, each waiting only for its own z_k: the
-// latency-bound small levels overlap the bandwidth-bound finest ones.
+// latency-bound small levels overlap the bandwidth-bound finest ones.  The
+// tail is enqueued first and the finest correction leaves some workgroup
+// slots on every CU free, so that the chain of small launches is not held
+// back behind the finest correction's long-lived workgroups.
 template <typename T>
 int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
@@ -925,19 +933,6 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             return fail(MGR_ERR_CAPTURE, "auxiliary streams not created and the stream is capturing; call mgr_prepare first");
         MGR_TRY(aux_stream(&aux), "auxiliary stream");
         MGR_TRY(hipEventRecord(aux->start, st), "fork event");
-        MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
-        if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
-        for (int i = 0; i < kt; i++) {
-            const int k = (i == 0) ? 0 : kt - i;  // finest first (own stream), then coarsest first
-            hipStream_t sk = (k == 0) ? aux->s0 : aux->s;
-            View3 cv = level_view(p, k);
-            T* z = ws + p.Zrec[(size_t)k];
-            int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z);
-            if (rc) return rc;
-            rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2);
-            if (rc) return rc;
-            MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
-        }
     }
     if (kt < L) {
         TailArgs<T> a = tail_args<T>(p, kt, src, dst);
@@ -948,6 +943,23 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
         MGR_TRY(timed(KC_COPY_VIEW, L, st,
                       [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
                 "coarsest gather");
+    }
+    if (kt > 0) {
+        MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
+        if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
+        const int reserve = g_rec_reserve.load();
+        for (int i = 0; i < kt; i++) {
+            const int k = (i == 0) ? 0 : kt - i;  // finest first (own stream), then coarsest first
+            hipStream_t sk = (k == 0) ? aux->s0 : aux->s;
+            View3 cv = level_view(p, k);
+            T* z = ws + p.Zrec[(size_t)k];
+            const int rsv = (k == 0 && kt > 1) ? reserve : 0;
+            int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z, rsv);
+            if (rc) return rc;
+            rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, rsv);
+            if (rc) return rc;
+            MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
+        }
     }
     for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
@@ -2514,6 +2526,11 @@ void mgr_finalize(void)
     }
     g_tm.ev.clear();
     g_tm.on = false;
+}
+
+int mgr_set_recompose_reserve(int slots)
+{
+    return g_rec_reserve.exchange(std::min(std::max(slots, 0), 8));
 }
 
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes)

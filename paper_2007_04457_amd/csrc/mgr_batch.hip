@@ -152,14 +152,23 @@ k_batch(const BatchKernelArgs<T>* __restrict__ A, int first)
     }
 }
 
-// Device side of the queue protocol (mgr_queue.h): agent-scope atomics on
-// the plan's queue words; polls sleep between loads.
+// Device side of the queue protocol (mgr_queue.h), run by a whole wave:
+// every value it returns is wave-uniform (one lane does each atomic and the
+// result is broadcast), so the loops and branches around it are uniform.
+// Agent-scope atomics; polls are relaxed loads (no cache invalidation) with a
+// sleep between them.
 struct DevQueueOps {
-    __device__ int load_relaxed(int* p) const { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ static bool leader() { return (threadIdx.x & 63) == 0; }
+    __device__ int load_relaxed(int* p) const
+    {
+        return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
     __device__ void fence_acquire() const { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
     __device__ int fetch_add_relaxed(int* p, int v) const
     {
-        return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int r = 0;
+        if (leader()) r = __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __builtin_amdgcn_readfirstlane(r);
     }
     // release at agent scope (one write-back of this XCD's L2), waited for
     // explicitly before the counter moves
@@ -167,16 +176,17 @@ struct DevQueueOps {
     {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __builtin_amdgcn_s_waitcnt(0);
-        (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (leader()) (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ void store_relaxed(int* p, int v) const
     {
-        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (leader()) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ void cas_relaxed(int* p, int expect, int v) const
     {
-        (void)__hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (leader())
+            (void)__hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ void pause() const { __builtin_amdgcn_s_sleep(2); }
 };
@@ -198,26 +208,36 @@ __device__ __forceinline__ void run_item(const BatchKernelArgs<T>* A, const Batc
 // The persistent form: every workgroup takes items from the queue until it
 // is empty (or the run is aborted), waiting for each item's dependency
 // group first.  The grid size is free (a workgroup takes an item only while
-// it runs).  After an item every thread waits until its own memory
-// operations have completed (so its stores are in the L2), the barrier then
-// lets thread 0 release them at agent scope with one write-back of the L2
-// before it marks the item finished; thread 0's acquire after the wait
-// precedes the barrier that starts the next item for every thread.
+// it runs).  Wave 0 takes and finishes items as a whole wave (the branch on
+// the wave index is uniform); the item index is broadcast through LDS and
+// read back as a uniform value, so the loop's exit and every branch around
+// its barriers are uniform: with a per-thread index the compiler may
+// restructure the loop so that the lanes of one wave take different paths
+// around a barrier, and the wave never reconverges.  After an item every
+// thread waits until its own memory operations have completed (its stores
+// are then in the L2), the barrier then lets wave 0 release them at agent
+// scope with one write-back of the L2 before it marks the item finished;
+// wave 0's acquire after the wait precedes the barrier that starts the next
+// item for every thread.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_batch_queue(const BatchKernelArgs<T>* __restrict__ A, QueueTables qt, QueueState qs, unsigned limit)
 {
     __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (;;) {
-        if (threadIdx.x == 0) s_item = queue_take(qt, qs, limit, DevQueueOps{});
+        if (wave == 0) {
+            const int t = queue_take(qt, qs, limit, DevQueueOps{});
+            if (DevQueueOps::leader()) s_item = t;
+        }
         __syncthreads();
-        const int i = s_item;
-        if (i < 0) return;
+        const int i = __builtin_amdgcn_readfirstlane(s_item);
+        if (i < 0) break;
         run_item(A, A->items + i);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no memory operation moves below the wait
         __builtin_amdgcn_s_waitcnt(0);             // this wave's loads and stores completed
         __syncthreads();
-        if (threadIdx.x == 0) queue_finish(qt, qs, i, DevQueueOps{});
+        if (wave == 0) queue_finish(qt, qs, i, DevQueueOps{});
     }
 }
 

@@ -83,9 +83,12 @@ struct SolveTables {
     int S;
 };
 
-// In-place correction solve of F along dimension d.
+// In-place correction solve of F along dimension d.  reserve: workgroup
+// slots per CU that a launch sized to the resident capacity leaves free (for
+// kernels on other streams that run alongside).
 template <typename T>
-hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st);
+hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st,
+                                    int reserve = 0);
 // All active dimensions of a small coarse grid in one workgroup (order:
 // dimensions dims[0], dims[1], ... of the nd listed), each fibre by the same
 // segment arithmetic as launch_solve_partitioned; returns hipErrorNotSupported
@@ -134,8 +137,9 @@ template <typename T>
 hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, const T* const* src, T* const* dst,
                              int n, bool decompose, hipStream_t st);
 
+// reserve: as for launch_solve_partitioned
 template <typename T>
-hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
+hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st, int reserve = 0);
 // One adjoint level step (mgr_adjoint.hip): g / gv the input at the level
 // grid's fine nodes, y the solved corrections and G the coarse-node input
 // (packed coarse grid yv), O / ov the level-grid output (not overlapping g).
@@ -431,6 +435,6 @@ hipError_t launch_gen_scatter(T* full, T* W, const T* Z, const GenLevel<T>& a, i
 // packed (outer, n, inner) box, in place; Yb as for launch_solve_partitioned.
 template <typename T>
 hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, SolveTables<T> tb, T* Yb,
-                               hipStream_t st);
+                               hipStream_t st, int reserve = 0);
 
 }  // namespace mgr

@@ -51,7 +51,8 @@ struct QueueState {
 };
 
 // Takes the next item and waits for its dependencies; -1 when the workgroup
-// should stop (queue empty, run aborted, or this wait timed out).
+// should stop (queue empty, run aborted, or this wait timed out).  On the
+// device a whole wave runs it and every value involved is wave-uniform.
 template <class Ops>
 __host__ __device__ inline int queue_take(const QueueTables& t, const QueueState& s, unsigned limit, Ops ops)
 {
@@ -76,9 +77,9 @@ __host__ __device__ inline int queue_take(const QueueTables& t, const QueueState
     return i;
 }
 
-// Marks item i finished: called by one thread once every write of the item
-// by every thread of the workgroup has completed (the caller waits for
-// them), with a release at agent scope.
+// Marks item i finished, once every write of the item by every thread of
+// the workgroup has completed (the caller waits for them), with a release at
+// agent scope (on the device: a whole wave, one lane doing the atomic).
 template <class Ops>
 __host__ __device__ inline void queue_finish(const QueueTables& t, const QueueState& s, int i, Ops ops)
 {

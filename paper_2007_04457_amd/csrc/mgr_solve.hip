@@ -45,17 +45,28 @@ k_solve_strided_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb)
 }
 
 
-// A block takes whole rows (rows_per_block * S lanes); their data are one
-// contiguous span of F, staged through LDS with one pad element per 32 so
-// that each lane's segment reads are bank-conflict free.
+// A workgroup takes blocks of whole rows (rows_per_block * S lanes), one
+// after the other with the next block's loads in flight; a block's data are
+// one contiguous span of F, staged through LDS with one pad element per 32
+// so that each lane's segment reads are bank-conflict free.
 template <typename T, bool kLdsTab>
 __global__ void __launch_bounds__(kBlk)
 k_solve_rows_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb, int rows_per_block)
 {
     __shared__ RowsSmem<T, rows_span<T>(), kLdsTab> sm;
-    const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
-    const int nrows = (int)min((int64_t)rows_per_block, m.nfib - row0);
-    solve_rows_tile<T, rows_span<T>(), kLdsTab>(F, m, tb, row0, nrows, sm);
+    solve_rows_loop<T, rows_span<T>(), kLdsTab>(F, m, tb, rows_per_block, sm);
+}
+
+// Workgroups of the rows kernel one CU holds (cached per kernel).
+template <typename K>
+int rows_resident(K kern, int& cache)
+{
+    if (cache == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBlk, 0) != hipSuccess || n <= 0) n = 2;
+        cache = n;
+    }
+    return cache;
 }
 
 template <typename T>
@@ -156,17 +167,17 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
 // Solve along dimension d of the packed array F (shape fv.n), in place.  Yb
 // is scratch of at least 2 * S * (number of fibres) elements.
 template <typename T>
-hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st)
+hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st, int reserve)
 {
     int64_t inner = 1, outer = 1;
     for (int e = d + 1; e < 3; e++) inner *= fv.n[e];
     for (int e = 0; e < d; e++) outer *= fv.n[e];
-    return launch_solve_fibres<T>(F, fv.n[d], inner, outer, tb, Yb, st);
+    return launch_solve_fibres<T>(F, fv.n[d], inner, outer, tb, Yb, st, reserve);
 }
 
 template <typename T>
 hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, SolveTables<T> tb, T* Yb,
-                               hipStream_t st)
+                               hipStream_t st, int reserve)
 {
     FibreMap m;
     m.n = n;
@@ -179,11 +190,16 @@ hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, So
         // workgroups per CU, so that small levels still spread over the chip
         const int64_t share = (m.nfib + 2 * (int64_t)device_cu_count() - 1) / (2 * (int64_t)device_cu_count());
         const int rpb = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(kBlk / m.S), (int64_t)(rows_span<T>() / m.n), share}));
-        const unsigned nb = (unsigned)((m.nfib + rpb - 1) / rpb);
+        const int64_t nb = (m.nfib + rpb - 1) / rpb;
+        // one round of resident workgroups, each looping over blocks
+        static int occ_t = 0, occ_g = 0;
+        const int res = (m.S <= kMaxSegWG) ? rows_resident(k_solve_rows_wg<T, true>, occ_t)
+                                           : rows_resident(k_solve_rows_wg<T, false>, occ_g);
+        const unsigned grid = (unsigned)std::min<int64_t>(nb, (int64_t)std::max(1, res - reserve) * device_cu_count());
         if (m.S <= kMaxSegWG)
-            hipLaunchKernelGGL((k_solve_rows_wg<T, true>), dim3(nb), dim3(kBlk), 0, st, F, m, tb, rpb);
+            hipLaunchKernelGGL((k_solve_rows_wg<T, true>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
         else
-            hipLaunchKernelGGL((k_solve_rows_wg<T, false>), dim3(nb), dim3(kBlk), 0, st, F, m, tb, rpb);
+            hipLaunchKernelGGL((k_solve_rows_wg<T, false>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
         return hipGetLastError();
     }
     if (m.inner > 1 && m.S <= kMaxSegWG) {
@@ -259,12 +275,12 @@ template hipError_t launch_solve_small<float>(float*, View3, const int*, int, co
 template hipError_t launch_solve_small<double>(double*, View3, const int*, int, const SolveTables<double>*,
                                                hipStream_t);
 template hipError_t launch_solve_fibres<float>(float*, int64_t, int64_t, int64_t, SolveTables<float>, float*,
-                                               hipStream_t);
+                                               hipStream_t, int);
 template hipError_t launch_solve_fibres<double>(double*, int64_t, int64_t, int64_t, SolveTables<double>, double*,
-                                                hipStream_t);
+                                               hipStream_t, int);
 template hipError_t launch_solve_partitioned<float>(float*, View3, int, SolveTables<float>, float*,
-                                                    hipStream_t);
+                                                    hipStream_t, int);
 template hipError_t launch_solve_partitioned<double>(double*, View3, int, SolveTables<double>, double*,
-                                                     hipStream_t);
+                                                    hipStream_t, int);
 
 }  // namespace mgr

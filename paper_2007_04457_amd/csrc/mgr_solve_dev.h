@@ -166,21 +166,24 @@ __device__ __forceinline__ void rows_load(const T* __restrict__ F, int64_t row0,
 {
     // one descriptor over the span (past its end the loads read zero), one
     // 32-bit offset per load
+    // (the q-th load's distance from the first goes into the scalar offset,
+    // so the lanes keep one address register for all of them)
     const __amdgpu_buffer_rsrc_t r = make_rsrc(F + row0 * n, (unsigned)span * (unsigned)sizeof(T));
     const unsigned o = threadIdx.x * (unsigned)sizeof(T);
 #pragma unroll
-    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) tmp[q] = buf_load<T>(r, o + (unsigned)(q * kBlk * sizeof(T)));
+    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) tmp[q] = buf_load_so<T>(r, o, (unsigned)(q * kBlk * sizeof(T)));
 }
 
 template <typename T, int kSpan, bool kLdsTab>
 __device__ __forceinline__ void rows_stage(const T (&tmp)[(kSpan + kBlk - 1) / kBlk], int span,
                                            RowsSmem<T, kSpan, kLdsTab>& sm)
 {
+    // padded(q kBlk + t) = q (kBlk + kBlk / 32) + padded(t): one address
+    // register, the rest in the instructions' offsets
+    T* const f = sm.f + padded((int)threadIdx.x);
 #pragma unroll
-    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) {
-        const int e = q * kBlk + (int)threadIdx.x;
-        if (e < span) sm.f[padded(e)] = tmp[q];
-    }
+    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++)
+        if (q * kBlk + (int)threadIdx.x < span) f[q * (kBlk + kBlk / 32)] = tmp[q];
 }
 
 template <typename T, int kSpan, bool kLdsTab>
@@ -208,13 +211,16 @@ __device__ __forceinline__ void rows_tables(const FibreMap& m, const SolveTables
 
 // The solve of the staged rows, in LDS.  Starts after a barrier that
 // follows the staging, ends with the solution in sm.f and a barrier.
+// tid: threadIdx.x (a caller in a loop passes it through an opaque copy, so
+// that the compiler does not hoist the per-slot LDS addresses out of the
+// loop and keep them all in registers).
 template <typename T, int kSpan, bool kLdsTab>
 __device__ __forceinline__ void rows_solve_lds(const FibreMap& m, const SolveTables<T>& tb, int nrows,
-                                               RowsSmem<T, kSpan, kLdsTab>& sm)
+                                               RowsSmem<T, kSpan, kLdsTab>& sm, int tid)
 {
     auto bar = [] { __syncthreads(); };
     const int n = (int)m.n;
-    const int r = threadIdx.x / m.S, s = threadIdx.x % m.S;
+    const int r = tid / m.S, s = tid % m.S;
     const bool active = r < nrows;
     const int rr = active ? r : 0;
     int lo, len;
@@ -229,12 +235,12 @@ __device__ __forceinline__ void rows_solve_lds(const FibreMap& m, const SolveTab
 #pragma unroll
     for (int q = 0; q < kSlot; q++) v[q] = sm.f[padded(rr * n + lo + min(q, len - 1))];
     const T ylast = seg_solve(v, tL, tU, tI);
-    sm.end[0][threadIdx.x] = v[0];
-    sm.end[1][threadIdx.x] = ylast;
+    sm.end[0][tid] = v[0];
+    sm.end[1][tid] = ylast;
     bar();
     if (active && s == 0 && m.S > 1) {
         // row r's separators live in sm.f at r*n + k*kSeg
-        const int t0 = threadIdx.x;
+        const int t0 = tid;
         T gg = T(0);
         for (int k = 1; k < m.S; k++) {
             const int e = padded(r * n + k * kSeg);
@@ -283,8 +289,41 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
     }
     rows_tables(m, tb, sm);
     __syncthreads();
-    rows_solve_lds<T, kSpan, kLdsTab>(m, tb, nrows, sm);
+    rows_solve_lds<T, kSpan, kLdsTab>(m, tb, nrows, sm, (int)threadIdx.x);
     rows_store(F, row0, span, n, sm);
+}
+
+// The per-level launch: each workgroup runs blocks blockIdx.x, + gridDim.x,
+// ... (every block rpb rows, the last one fewer), with the loads of its next
+// block issued right after the current block is staged, so that they are in
+// flight during the solve and the stores.  A block past the last reads
+// through an empty descriptor (no memory access), so the loads stay
+// unconditional.
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void solve_rows_loop(T* __restrict__ F, const FibreMap& m, const SolveTables<T>& tb,
+                                                int rpb, RowsSmem<T, kSpan, kLdsTab>& sm)
+{
+    const int n = (int)m.n;
+    const int64_t nblk = (m.nfib + rpb - 1) / rpb;
+    auto span_of = [&](int64_t b) {
+        return b < nblk ? (int)min((int64_t)rpb, m.nfib - b * rpb) * n : 0;
+    };
+    rows_tables(m, tb, sm);
+    T tmp[(kSpan + kBlk - 1) / kBlk];
+    int64_t b = blockIdx.x;
+    rows_load<T, kSpan>(F, b < nblk ? b * rpb : 0, span_of(b), n, tmp);
+    for (; b < nblk; b += gridDim.x) {
+        const int span = span_of(b);
+        rows_stage<T, kSpan, kLdsTab>(tmp, span, sm);
+        const int64_t bn = b + gridDim.x;
+        rows_load<T, kSpan>(F, bn < nblk ? bn * rpb : 0, span_of(bn), n, tmp);
+        __syncthreads();
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        rows_solve_lds<T, kSpan, kLdsTab>(m, tb, span / n, sm, tid);
+        rows_store(F, b * rpb, span, n, sm);
+        __syncthreads();  // every lane has read sm.f before the next block is staged
+    }
 }
 
 // ---- long fibres: three launches through global memory ---------------------

@@ -246,9 +246,9 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     // One buffer descriptor per array and plane, holding the plane's bytes;
     // each row is reached through the instruction's scalar offset (the row's
     // byte offset in the plane, kept in a scalar register for the whole
-    // kernel).  A row outside the grid loads the nearest grid row instead and
-    // its values are replaced by zero where they are used (rin), so the
-    // loads stay unconditional and need no per-row lane offsets.
+    // kernel).  A row outside the grid loads a grid row instead and its
+    // values are replaced by zero where they are used (rin), so the loads
+    // stay unconditional and need no per-row lane offsets.
     const unsigned spanA = (unsigned)((m1 - 1) * as1 + (m2 - 1) * as2 + 1) * S;
     const unsigned spanC = (unsigned)((m1 - 1) * cs1 + (m2 - 1) * cs2 + 1) * S;
     const unsigned spanW = (unsigned)(((m1 - 1) / 2) * ws1 + ((m2 - 1) / 2) * ws2 + 1) * S;
@@ -262,7 +262,10 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
         gr[k] = R0 + r;
         rin[k] = r < NR && gr[k] >= 0 && gr[k] < m1;
         rown[k] = rin[k] && gr[k] >= oR0 && gr[k] < oR1;
-        const int grc = min(max(gr[k], 0), m1 - 1);
+        // a row past the staged region re-reads this wave's previous row (the
+        // same lines: no further memory traffic), a row outside the grid the
+        // nearest grid row
+        const int grc = min(max(r < NR ? gr[k] : gr[k] - RW, 0), m1 - 1);
         soA[k] = (unsigned)uni((int)((unsigned)(grc * as1) * S));
         soC[k] = (unsigned)uni((int)((unsigned)(grc * cs1) * S));
         soW[k] = (unsigned)uni((int)((unsigned)((grc >> 1) * ws1) * S));
