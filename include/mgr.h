@@ -123,6 +123,25 @@ int mgr_recompose_adjoint(const void* src, void* dst, int dtype, int ndim,
                           const int64_t* shape, const double* const* coords,
                           int nlevels, void* stream);
 
+/* Allocation-free decomposition, for callers that cannot allocate device
+ * memory (code under stream capture, allocation-free serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, arithmetic and result
+ * as mgr_decompose (bit for bit), but the problem's tables and workspace
+ * live in one library-owned device array of MGR_NOALLOC_SCRATCH_BYTES per
+ * device (held from the first call on a device until the process ends)
+ * instead of the per-problem cache: the call never allocates device memory.
+ * A problem whose tables plus decomposition workspace exceed the array is
+ * refused with MGR_ERR_ALLOC before anything is enqueued (513^3 float32
+ * needs about 152 MiB; 513^3 float64 does not fit).  Every call on a device
+ * shares that device's array and the array keeps the last call's contents:
+ * calls that overlap on one device (different streams, or threads) race.
+ * The tables are copied into the array from host memory when the previous
+ * call on the device was another problem. */
+#define MGR_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int mgr_decompose_noalloc(const void* src, void* dst, int dtype, int ndim,
+                          const int64_t* shape, const double* const* coords,
+                          int nlevels, void* stream);
+
 /* Builds and uploads the tables and allocates the workspace of a problem
  * (synchronously), and creates the recomposition's streams of the current
  * device, so that later calls on a capturing stream allocate and create

@@ -20,7 +20,7 @@ from ._lib import MgrError, MGR_F32, MGR_F64
 __all__ = [
     "MgrError", "MGR_F32", "MGR_F64",
     "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_recompose_adjoint",
-    "mgr_prepare",
+    "mgr_decompose_noalloc", "mgr_prepare",
     "mgr_class_map", "class_masks", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
     "mgr_set_recompose_reserve",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
@@ -72,6 +72,12 @@ def _call(fn_name, src, dst, coords, nlevels):
 def mgr_decompose(src, dst, coords=None, nlevels=-1):
     """dst <- decomposition of src (dst may be src).  See include/mgr.h."""
     return _call("mgr_decompose", src, dst, coords, nlevels)
+
+
+def mgr_decompose_noalloc(src, dst, coords=None, nlevels=-1):
+    """mgr_decompose through the library's fixed device scratch array: the
+    call allocates no device memory (see include/mgr.h)."""
+    return _call("mgr_decompose_noalloc", src, dst, coords, nlevels)
 
 
 def mgr_recompose(src, dst, coords=None, nlevels=-1):

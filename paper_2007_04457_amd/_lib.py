@@ -36,7 +36,8 @@ def load():
     i64p = ctypes.POINTER(ctypes.c_int64)
     dpp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
     vp = ctypes.c_void_p
-    for name in ("mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_recompose_adjoint"):
+    for name in ("mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_recompose_adjoint",
+                 "mgr_decompose_noalloc"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64p, dpp, ctypes.c_int, vp]
         fn.restype = ctypes.c_int

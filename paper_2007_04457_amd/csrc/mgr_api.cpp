@@ -2143,6 +2143,95 @@ int run_recompose_level(const void* src_, void* dst_, int ndim, const int64_t* s
     return run_recompose<T>(*ps, tmp, dst, st);
 }
 
+// ---- allocation-free decomposition ------------------------------------------
+// For callers that cannot allocate device memory: the tables and the
+// decomposition's workspace of the problem live in one file-scope device
+// array instead of the per-problem cache.  Each device holds its own copy of
+// the array, at its own address, found once per device with
+// hipGetSymbolAddress; host code only ever uses that address (the array's
+// name in host code is a host-side stand-in).  Every call on a device shares
+// its array: calls that overlap on one device race.
+constexpr size_t kScratchBytes = (size_t)MGR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchDev {
+    void* ptr = nullptr;      // device address of `scratch` on this device
+    std::string tables_key;   // problem whose tables the array holds now
+};
+std::mutex g_scratch_mu;
+ScratchDev g_scratch[64];
+// host halves of the allocation-free plans (layouts and host tables, no
+// device memory), per problem
+struct NoAllocPlan {
+    Plan p;
+    std::vector<unsigned char> host_tables;
+};
+std::map<std::string, std::unique_ptr<NoAllocPlan>> g_noalloc_plans;
+
+template <typename T>
+void noalloc_layout(NoAllocPlan& q, const double* const* coords)
+{
+    std::vector<T> host;
+    plan_layout<T>(q.p, coords, true, host);
+    q.host_tables.resize(host.size() * sizeof(T));
+    if (!host.empty()) std::memcpy(q.host_tables.data(), host.data(), q.host_tables.size());
+}
+
+int run_decompose_noalloc(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                          const double* const* coords, int nlevels, void* stream)
+{
+    g_err.clear();
+    if (!src || !dst) return fail(MGR_ERR_ARG, "src or dst is NULL");
+    int rc = validate(dtype, ndim, shape, coords, &nlevels);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(MGR_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchDev& sd = g_scratch[dev];
+    if (!sd.ptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(MGR_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        sd.ptr = ptr;
+    }
+    const std::string key = plan_key(dev, dtype, ndim, shape, coords, nlevels);
+    auto it = g_noalloc_plans.find(key);
+    if (it == g_noalloc_plans.end()) {
+        auto q = std::make_unique<NoAllocPlan>();
+        plan_dims(q->p, dev, dtype, ndim, shape, nlevels);
+        if (dtype == MGR_F32)
+            noalloc_layout<float>(*q, coords);
+        else
+            noalloc_layout<double>(*q, coords);
+        it = g_noalloc_plans.emplace(key, std::move(q)).first;
+    }
+    Plan& p = it->second->p;
+    const size_t tab = align_up(p.tables_bytes, 256);
+    if (tab + p.ws_bytes > kScratchBytes)
+        return fail(MGR_ERR_ALLOC, "problem needs " + std::to_string(tab + p.ws_bytes) +
+                                       " bytes of tables and workspace; the allocation-free scratch holds " +
+                                       std::to_string(kScratchBytes));
+    p.tables = sd.ptr;
+    p.ws = (unsigned char*)sd.ptr + tab;
+    if (sd.tables_key != key) {
+        // in stream order before the kernels that read them; the host copy
+        // stays alive in the plan
+        if (p.tables_bytes) {
+            e = hipMemcpyAsync(p.tables, it->second->host_tables.data(), p.tables_bytes, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) {
+                sd.tables_key.clear();
+                return hip_fail(e, "upload tables to the scratch array");
+            }
+        }
+        sd.tables_key = key;
+    }
+    return dtype == MGR_F32 ? run_decompose<float>(p, src, dst, st) : run_decompose<double>(p, src, dst, st);
+}
+
 // The work items, waves and queue groups of a batch, built on the host
 // alone (no device memory: plans keep only their layouts and the pointers in
 // the item arguments are never used), for the host check of the queue.
@@ -2278,6 +2367,18 @@ int mgr_decompose(const void* src, void* dst, int dtype, int ndim, const int64_t
 {
     try {
         return run(DIR_DEC, src, dst, dtype, ndim, shape, coords, nlevels, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(MGR_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_decompose_noalloc(const void* src, void* dst, int dtype, int ndim, const int64_t* shape,
+                          const double* const* coords, int nlevels, void* stream)
+{
+    try {
+        return run_decompose_noalloc(src, dst, dtype, ndim, shape, coords, nlevels, stream);
     } catch (const std::bad_alloc&) {
         return fail(MGR_ERR_ALLOC, "host allocation failed");
     } catch (...) {
@@ -2518,6 +2619,13 @@ void mgr_finalize(void)
         g_plans.clear();
         for (auto& kv : g_gen_plans) free_gen_plan(*kv.second);
         g_gen_plans.clear();
+    }
+    {
+        // the allocation-free plans are host memory only; the scratch array
+        // itself stays with the device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        g_noalloc_plans.clear();
+        for (ScratchDev& sd : g_scratch) sd.tables_key.clear();
     }
     std::lock_guard<std::mutex> lk(g_tm_mu);
     for (auto& e : g_tm.ev) {
