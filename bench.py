@@ -138,17 +138,22 @@ def batched_vs_serial(mgr, torch, synth):
            "serial_GBps": round(nbytes / t_serial / 1e6, 2)}
     want = [mgr.decompose(x) for x in xs]
     # the autotuner picks the launch form and chunk (model fitted to probe
-    # runs, top three timed); both forms are then timed at their own best
-    # chunk as well
+    # runs of each form, top three timed); both forms are then timed at the
+    # best chunk of a plain sweep as well
     tuned_chunk, _, _ = plan.autotune(xs, ys, top_k=3)
     tuned_form, model = plan.tuning()
     out["autotune"] = {"form": "persistent" if tuned_form else "waves", "chunk": tuned_chunk,
                        "model_ms_a_perbyte_peritem": {k: [float(f"{v:.4g}") for v in m] for k, m in model.items()}}
-    for mode in ("waves",):
+    for mode in ("waves", "persistent"):
         plan.set_mode(mode == "persistent")
-        chunk, launches, items = plan.autotune(xs, ys, top_k=3) if mode != out["autotune"]["form"] else \
-            (tuned_chunk,) + tuple(plan.config()[1:])
-        plan.set_mode(mode == "persistent")
+        sweep = {}
+        for c in (2, 4, 8, 16, 32, 64, 128):
+            plan.set_config(c)
+            sweep[c] = event_ms(torch, lambda: plan.decompose(xs, ys), reps=3, warmup=1)
+        plan.check()
+        chunk = min(sweep, key=sweep.get)
+        plan.set_config(chunk)
+        _, launches, items = plan.config()
         t_batch = event_ms(torch, lambda: plan.decompose(xs, ys))
         g = torch.cuda.CUDAGraph()
         st = torch.cuda.Stream()
@@ -162,10 +167,11 @@ def batched_vs_serial(mgr, torch, synth):
         out[mode] = {"batched_ms": round(t_batch, 4), "graph_ms": round(t_graph, 4),
                      "graph_GBps": round(nbytes / t_graph / 1e6, 2),
                      "speedup_vs_serial": round(t_serial / t_graph, 3), "chunk": chunk,
+                     "chunk_sweep_ms": {str(c): round(v, 3) for c, v in sweep.items()},
                      "launches": launches, "items": items,
                      "matches_serial_bitwise": bool(ok)}
     plan.close()
-    best = "waves"
+    best = min(("waves", "persistent"), key=lambda m: out[m]["graph_ms"])
     out["best"] = best
     out["graph_ms"] = out[best]["graph_ms"]
     out["graph_GBps"] = out[best]["graph_GBps"]

@@ -248,13 +248,16 @@ void mgr_finalize(void);
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes);
 
 /* Workgroup slots per compute unit that the recomposition's finest-level
- * correction leaves free.  The recomposition computes the finest level
- * step's correction on one stream while the coarser level steps run on
- * others; the finest correction's launches are sized to the device's
- * resident capacity, and without free slots every small launch of the
- * coarser levels waits for its workgroups to finish.  Clamped to 0..8;
- * default 2.  Returns the previous value.  Process-wide; affects calls
- * enqueued afterwards; results do not depend on it. */
+ * streaming launch leaves free.  The recomposition computes the finest
+ * level step's correction on one stream while the coarser level steps run
+ * on others; the finest streaming launch is sized to the device's resident
+ * capacity, so without free slots the small launches of the coarser levels
+ * wait for its workgroups.  A tuning knob: on the MI355X at 513^3 a value of
+ * 4 shortens the FP32 recomposition by about 3% and lengthens the FP64 one
+ * by about 6% (the coarser launches then mostly wait on memory, not on
+ * slots).  Clamped to 0..8; default 0.  Returns the previous value.
+ * Process-wide; affects calls enqueued afterwards; results do not depend on
+ * it. */
 int mgr_set_recompose_reserve(int slots);
 
 /* ---- batched decomposition ----------------------------------------------
@@ -293,13 +296,14 @@ int mgr_batch_plan_create(int nfields, const int* ndim, const int64_t* const* sh
  * (out of place).  Calls on one plan must be ordered on one stream. */
 int mgr_batch_decompose(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream);
 
-/* Autotuner (the model-then-measure search of Sec. III-C): for the plan's
- * launch form (mgr_batch_set_mode) it times three probe chunk lengths
- * (coarse planes per streaming item: 2, 16, 128) on these fields, fits a
- * transaction model time = a + x * bytes + y * items to them (bytes: the
- * streaming items' traffic with their re-read plane halos; items: streaming
- * items), ranks every chunk length 2..128 by the fitted model, times the best
- * top_k, and keeps the fastest chunk measured.  Synchronous; overwrites
+/* Autotuner (the model-then-measure search of Sec. III-C): for each launch
+ * form (waves, persistent; mgr_batch_set_mode) it times three probe chunk
+ * lengths (coarse planes per streaming item: 2, 16, 128) on these fields,
+ * fits a transaction model time = a + x * bytes + y * items to them (bytes:
+ * the streaming items' traffic with their re-read plane halos; items:
+ * streaming items), ranks every chunk length 2..128 by the fitted model and
+ * times the best top_k; the plan keeps the fastest (form, chunk) measured,
+ * with the persistent form's poll bound unchanged.  Synchronous; overwrites
  * dst. */
 int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream,
                        int top_k);

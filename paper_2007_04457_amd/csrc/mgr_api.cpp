@@ -682,12 +682,17 @@ int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 a
 }
 
 // Correction solves of level step k on F along every dimension, in place.
+// whole_cu: a small grid may be solved by one workgroup that needs a whole
+// CU (all dimensions in one launch); a caller whose launches share the
+// device with long-running kernels on another stream passes false, since
+// such a workgroup waits until one CU has drained completely (the
+// per-dimension launches give the same values).
 template <typename T>
-int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = nullptr, int reserve = 0)
+int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = nullptr, bool whole_cu = true)
 {
     T* ws = (T*)p.ws;
     View3 fv = packed(p.lv[(size_t)k].mc);
-    {
+    if (whole_cu) {
         // small coarse grids: every dimension in one launch when it fits
         int dims[3], nd = 0;
         SolveTables<T> tbs[3];
@@ -708,7 +713,7 @@ int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = 
         if (!p.active[d]) continue;
         SolveTables<T> tb = solve_tables_of<T>(p, k, d);
         MGR_TRY(timed(KC_SOLVE, k, st,
-                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, Yb ? Yb : ws + p.Yb, st, reserve); }),
+                      [&] { return launch_solve_partitioned<T>(F, fv, d, tb, Yb ? Yb : ws + p.Yb, st); }),
                 "solve launch");
     }
     return MGR_OK;
@@ -902,10 +907,10 @@ bool aux_ready()
     return g_aux[dev].s != nullptr;
 }
 
-// Workgroup slots per CU that the recomposition's finest correction (sized
-// to the resident capacity) leaves free for the coarse levels running
+// Workgroup slots per CU that the recomposition's finest streaming launch
+// (sized to the resident capacity) leaves free for the coarse levels running
 // alongside it (mgr_set_recompose_reserve).
-std::atomic<int> g_rec_reserve{2};
+std::atomic<int> g_rec_reserve{0};
 
 // Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
 // The correction z_k of every level step depends on the stored coefficients
@@ -914,9 +919,10 @@ std::atomic<int> g_rec_reserve{2};
 // first, on the other) while the caller's stream runs the coarsest levels
 // and the interpolations, each waiting only for its own z_k: the
 // latency-bound small levels overlap the bandwidth-bound finest ones.  The
-// tail is enqueued first and the finest correction leaves some workgroup
-// slots on every CU free, so that the chain of small launches is not held
-// back behind the finest correction's long-lived workgroups.
+// tail is enqueued first, the finest correction's streaming launch leaves
+// some workgroup slots on every CU free, and the coarser corrections use no
+// whole-CU workgroup, so that the chain of small launches is not held back
+// behind the finest correction's long-lived workgroups.
 template <typename T>
 int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
@@ -956,7 +962,7 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             const int rsv = (k == 0 && kt > 1) ? reserve : 0;
             int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z, rsv);
             if (rc) return rc;
-            rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, rsv);
+            rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, k == 0);
             if (rc) return rc;
             MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
         }
@@ -1801,6 +1807,12 @@ int batch_upload(BatchPlan& b, int chunk)
         e = hipMemcpy(d + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload batch tables");
     }
+    // the queue words start cleared (a fresh allocation may hold anything),
+    // so that mgr_batch_check reads no stale state before the first
+    // persistent run on these tables
+    const std::vector<int> zeros(3 + b.qneed.size(), 0);
+    e = hipMemcpy(d + b.off_qwords, zeros.data(), sizeof(int) * zeros.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clear queue words");
     b.waves = t.waves;
     b.n_items = (int)t.items.size();
     b.n_tail = (int)t.tail.size();
@@ -2777,8 +2789,8 @@ int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const
         double best = 1e300;
         int best_chunk = b->chunk, best_mode = b->persistent;
         const unsigned limit = b->poll_limit;
-        // the launch form the plan uses (mgr_batch_set_mode) is tuned
-        for (int mode = b->persistent; mode <= b->persistent && rc == MGR_OK; mode++) {
+        // both launch forms (waves, persistent), each with its own model
+        for (int mode = 0; mode <= 1 && rc == MGR_OK; mode++) {
             b->persistent = mode;
             b->poll_limit = limit;
             // fit the model to three probe configurations, rank every

@@ -83,12 +83,9 @@ struct SolveTables {
     int S;
 };
 
-// In-place correction solve of F along dimension d.  reserve: workgroup
-// slots per CU that a launch sized to the resident capacity leaves free (for
-// kernels on other streams that run alongside).
+// In-place correction solve of F along dimension d.
 template <typename T>
-hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st,
-                                    int reserve = 0);
+hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st);
 // All active dimensions of a small coarse grid in one workgroup (order:
 // dimensions dims[0], dims[1], ... of the nd listed), each fibre by the same
 // segment arithmetic as launch_solve_partitioned; returns hipErrorNotSupported
@@ -137,7 +134,8 @@ template <typename T>
 hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, const T* const* src, T* const* dst,
                              int n, bool decompose, hipStream_t st);
 
-// reserve: as for launch_solve_partitioned
+// reserve: workgroup slots per CU that the launch (sized to the resident
+// capacity) leaves free, for kernels on other streams that run alongside.
 template <typename T>
 hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st, int reserve = 0);
 // One adjoint level step (mgr_adjoint.hip): g / gv the input at the level
@@ -435,6 +433,6 @@ hipError_t launch_gen_scatter(T* full, T* W, const T* Z, const GenLevel<T>& a, i
 // packed (outer, n, inner) box, in place; Yb as for launch_solve_partitioned.
 template <typename T>
 hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, SolveTables<T> tb, T* Yb,
-                               hipStream_t st, int reserve = 0);
+                               hipStream_t st);
 
 }  // namespace mgr

@@ -167,17 +167,17 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
 // Solve along dimension d of the packed array F (shape fv.n), in place.  Yb
 // is scratch of at least 2 * S * (number of fibres) elements.
 template <typename T>
-hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st, int reserve)
+hipError_t launch_solve_partitioned(T* F, View3 fv, int d, SolveTables<T> tb, T* Yb, hipStream_t st)
 {
     int64_t inner = 1, outer = 1;
     for (int e = d + 1; e < 3; e++) inner *= fv.n[e];
     for (int e = 0; e < d; e++) outer *= fv.n[e];
-    return launch_solve_fibres<T>(F, fv.n[d], inner, outer, tb, Yb, st, reserve);
+    return launch_solve_fibres<T>(F, fv.n[d], inner, outer, tb, Yb, st);
 }
 
 template <typename T>
 hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, SolveTables<T> tb, T* Yb,
-                               hipStream_t st, int reserve)
+                               hipStream_t st)
 {
     FibreMap m;
     m.n = n;
@@ -195,7 +195,7 @@ hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, So
         static int occ_t = 0, occ_g = 0;
         const int res = (m.S <= kMaxSegWG) ? rows_resident(k_solve_rows_wg<T, true>, occ_t)
                                            : rows_resident(k_solve_rows_wg<T, false>, occ_g);
-        const unsigned grid = (unsigned)std::min<int64_t>(nb, (int64_t)std::max(1, res - reserve) * device_cu_count());
+        const unsigned grid = (unsigned)std::min<int64_t>(nb, (int64_t)res * device_cu_count());
         if (m.S <= kMaxSegWG)
             hipLaunchKernelGGL((k_solve_rows_wg<T, true>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
         else
@@ -275,12 +275,12 @@ template hipError_t launch_solve_small<float>(float*, View3, const int*, int, co
 template hipError_t launch_solve_small<double>(double*, View3, const int*, int, const SolveTables<double>*,
                                                hipStream_t);
 template hipError_t launch_solve_fibres<float>(float*, int64_t, int64_t, int64_t, SolveTables<float>, float*,
-                                               hipStream_t, int);
+                                               hipStream_t);
 template hipError_t launch_solve_fibres<double>(double*, int64_t, int64_t, int64_t, SolveTables<double>, double*,
-                                               hipStream_t, int);
+                                               hipStream_t);
 template hipError_t launch_solve_partitioned<float>(float*, View3, int, SolveTables<float>, float*,
-                                                    hipStream_t, int);
+                                                    hipStream_t);
 template hipError_t launch_solve_partitioned<double>(double*, View3, int, SolveTables<double>, double*,
-                                                    hipStream_t, int);
+                                                    hipStream_t);
 
 }  // namespace mgr
