@@ -143,7 +143,8 @@ def batched_vs_serial(mgr, torch, synth):
     tuned_chunk, _, _ = plan.autotune(xs, ys, top_k=3)
     tuned_form, model = plan.tuning()
     out["autotune"] = {"form": "persistent" if tuned_form else "waves", "chunk": tuned_chunk,
-                       "model_ms_a_perbyte_peritem": {k: [float(f"{v:.4g}") for v in m] for k, m in model.items()}}
+                       "model_ms_a_perbyte_peritem_perdepthplane": {k: [float(f"{v:.4g}") for v in m]
+                                                                     for k, m in model.items()}}
     for mode in ("waves", "persistent"):
         plan.set_mode(mode == "persistent")
         sweep = {}

@@ -297,11 +297,13 @@ int mgr_batch_plan_create(int nfields, const int* ndim, const int64_t* const* sh
 int mgr_batch_decompose(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream);
 
 /* Autotuner (the model-then-measure search of Sec. III-C): for each launch
- * form (waves, persistent; mgr_batch_set_mode) it times three probe chunk
- * lengths (coarse planes per streaming item: 2, 16, 128) on these fields,
- * fits a transaction model time = a + x * bytes + y * items to them (bytes:
- * the streaming items' traffic with their re-read plane halos; items:
- * streaming items), ranks every chunk length 2..128 by the fitted model and
+ * form (waves, persistent; mgr_batch_set_mode) it times five probe chunk
+ * lengths (coarse planes per streaming item: 2, 4, 16, 64, 128) on these
+ * fields, fits a transaction model time = a + x * bytes + y * items +
+ * z * depth to them with non-negative constants (bytes: the streaming items'
+ * traffic with their re-read plane halos; items: streaming items; depth: the
+ * planes the longest streaming item of each level step streams, summed over
+ * the level steps), ranks every chunk length 2..128 by the fitted model and
  * times the best top_k; the plan keeps the fastest (form, chunk) measured,
  * with the persistent form's poll bound unchanged.  Synchronous; overwrites
  * dst. */
@@ -309,8 +311,9 @@ int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const
                        int top_k);
 
 /* The launch form the plan uses (0 waves, 1 persistent) and the fitted model
- * constants of the last autotune of each form: model[3 * form + i] = a (ms),
- * x (ms per byte), y (ms per streaming item) (zeros for a form not tuned). */
+ * constants of the last autotune of each form (model: 8 doubles):
+ * model[4 * form + i] = a (ms), x (ms per byte), y (ms per streaming item),
+ * z (ms per plane of depth) (zeros for a form not tuned). */
 int mgr_batch_tuning(const mgr_batch_plan* plan, int* persistent, double* model);
 
 /* Current configuration: chunk length, kernel launches per call (besides
@@ -340,16 +343,20 @@ int mgr_batch_set_mode(mgr_batch_plan* plan, int persistent, unsigned poll_limit
 int mgr_batch_check(mgr_batch_plan* plan);
 
 /* Host check of the persistent form's scheduling protocol: builds the work
- * items, waves and dependency groups of a batch of these fields on the host
- * alone (no device is used) and runs the same queue functions the kernel
- * runs on nthreads host threads standing in for workgroups, each item
- * "executed" as a random delay.  The thread that takes item stall_item
- * (>= 0; -1 for none) stops without finishing it, as a workgroup that never
- * completes would.  Writes out[0] items run, out[1] items that started before
- * the items they depend on had finished, out[2] the error word (1 + the item
- * whose wait ran out, 0 if none), out[3] items never taken. */
+ * items, waves, queues (nqueues of them, 1..16: the device uses one per XCD)
+ * and dependency groups of a batch of these fields on the host alone (no
+ * device is used) and runs the same queue functions the kernel runs on
+ * nthreads host threads standing in for workgroups (thread t serves queue
+ * t mod nqueues), each item "executed" as a random delay.  The thread that
+ * takes queue position stall_item (>= 0; -1 for none; positions number the
+ * queues' items one queue after the other) stops without finishing it, as a
+ * workgroup that never completes would.  Writes out[0] items run, out[1]
+ * items that started before the items they depend on had finished, out[2]
+ * the error word (1 + the position whose wait ran out, 0 if none), out[3]
+ * positions never taken. */
 int mgr_batch_queue_check(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int dtype,
-                          int chunk, int nthreads, unsigned poll_limit, int stall_item, uint64_t seed, int64_t* out);
+                          int chunk, int nqueues, int nthreads, unsigned poll_limit, int stall_item, uint64_t seed,
+                          int64_t* out);
 
 /* Frees the plan (hipFree waits for work still using it). */
 void mgr_batch_plan_destroy(mgr_batch_plan* plan);

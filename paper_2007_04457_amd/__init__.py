@@ -416,11 +416,11 @@ Recompose = _LazyFunction("Recompose")
 
 
 def batch_queue_check(shapes, dtype_code=MGR_F32, nlevels=None, chunk=8, nthreads=8, poll_limit=0,
-                      stall_item=-1, seed=0):
+                      stall_item=-1, seed=0, nqueues=8):
     """Runs the persistent batch's scheduling protocol for these field shapes
-    on host threads (mgr_batch_queue_check; no device needed).  Returns
-    (items run, items started before their dependencies finished, error
-    word, items never taken)."""
+    on host threads (mgr_batch_queue_check; no device needed), with nqueues
+    queues.  Returns (items run, items started before their dependencies
+    finished, error word, queue positions never taken)."""
     import ctypes
     shapes = [tuple(int(n) for n in s) for s in shapes]
     nf = len(shapes)
@@ -429,7 +429,8 @@ def batch_queue_check(shapes, dtype_code=MGR_F32, nlevels=None, chunk=8, nthread
     shp_p = (ctypes.POINTER(ctypes.c_int64) * nf)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_int64)) for a in shp])
     nl = None if nlevels is None else (ctypes.c_int * nf)(*[int(x) for x in nlevels])
     out = (ctypes.c_int64 * 4)()
-    _lib.check(_lib.load().mgr_batch_queue_check(nf, nd, shp_p, nl, int(dtype_code), int(chunk), int(nthreads),
+    _lib.check(_lib.load().mgr_batch_queue_check(nf, nd, shp_p, nl, int(dtype_code), int(chunk), int(nqueues),
+                                                 int(nthreads),
                                                  int(poll_limit), int(stall_item), int(seed), out))
     return tuple(int(v) for v in out)
 
@@ -508,12 +509,13 @@ class BatchPlan:
 
     def tuning(self):
         """(persistent form in use, fitted model per form: {"waves": (a_ms,
-        ms_per_byte, ms_per_item), "persistent": (...)}) after autotune."""
+        ms_per_byte, ms_per_item, ms_per_depth_plane), "persistent": (...)})
+        after autotune."""
         import ctypes
         p = ctypes.c_int(0)
-        m = (ctypes.c_double * 6)()
+        m = (ctypes.c_double * 8)()
         _lib.check(_lib.load().mgr_batch_tuning(self._h, ctypes.byref(p), m))
-        return bool(p.value), {"waves": tuple(m[0:3]), "persistent": tuple(m[3:6])}
+        return bool(p.value), {"waves": tuple(m[0:4]), "persistent": tuple(m[4:8])}
 
     def set_mode(self, persistent, poll_limit=0):
         """persistent=True: one queue-driven launch for all items (see

@@ -104,7 +104,7 @@ def load():
     lib.mgr_batch_check.argtypes = [vp]
     lib.mgr_batch_check.restype = ctypes.c_int
     lib.mgr_batch_queue_check.argtypes = [ctypes.c_int, i32p, ctypes.POINTER(i64p), i32p, ctypes.c_int, ctypes.c_int,
-                                          ctypes.c_int, ctypes.c_uint, ctypes.c_int, ctypes.c_uint64, i64p]
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int, ctypes.c_uint64, i64p]
     lib.mgr_batch_queue_check.restype = ctypes.c_int
     lib.mgr_batch_plan_destroy.argtypes = [vp]
     lib.mgr_batch_plan_destroy.restype = None

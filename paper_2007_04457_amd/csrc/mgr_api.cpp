@@ -1550,40 +1550,117 @@ struct BatchPlan {
     int n_items = 0, n_tail = 0;
     int chunk = 8, tuned = 0;
     int64_t bytes = 0;             // input bytes of the batch
-    // persistent form (mgr_queue.h): group of each item, dependency group and
-    // size of each group (host copies for the host check), device offsets of
-    // those tables and of the queue words (next, abort, err, done[groups])
+    // persistent form (mgr_queue.h): queues (one per XCD), the item at each
+    // queue position and each queue's first position, the group of each
+    // position, dependency group and size of each group (host copies for the
+    // host check), device offsets of those tables and of the queue words
+    // (abort, err, next[kMaxQueues], done[groups])
     int persistent = 0;
     unsigned poll_limit = 1u << 20;
-    double model[2][3] = {{0, 0, 0}, {0, 0, 0}};  // fitted a (ms), x (ms/B), y (ms/item) per launch form
-    std::vector<int> qgrp, qdep, qneed;
-    size_t off_qgrp = 0, off_qdep = 0, off_qneed = 0, off_qwords = 0;
+    double model[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // fitted a, x, y, z (batch_terms) per launch form
+    int nq = 1, ran_persistent = 0;  // ran_persistent: a persistent run since the tables were uploaded
+    std::vector<int> qorder, qstart, qgrp, qdep, qneed;
+    size_t off_qorder = 0, off_qgrp = 0, off_qdep = 0, off_qneed = 0, off_qwords = 0;
 };
 
-// Groups of the item list for the queue: the items of one field within one
-// wave form a group, which depends on the previous group of the same field.
-void batch_groups(const std::vector<BatchItem>& items, const std::vector<std::pair<int, int>>& waves, int nfields,
-                  std::vector<int>& grp, std::vector<int>& dep, std::vector<int>& need)
+// Queues of the persistent form.  Each field goes to one of nq queues (one
+// per XCD), longest estimated work first to the least loaded queue; a
+// field's estimate is its streaming bytes plus, per stage, the bytes an XCD
+// moves in a stage's fixed latency (about 4 MB).  A queue lists its fields'
+// items wave by wave (keeping their order within a wave); the items of one
+// field within one wave form a group, which depends on the previous group
+// of the same field.  order: item at each position; start: each queue's
+// first position (nq + 1 entries); grp: group of each position.
+void batch_queues(const BatchPlan& b, const std::vector<BatchItem>& items,
+                  const std::vector<std::pair<int, int>>& waves, int nq, std::vector<int>& order,
+                  std::vector<int>& start, std::vector<int>& grp, std::vector<int>& dep, std::vector<int>& need)
 {
-    grp.assign(items.size(), 0);
-    dep.clear();
-    need.clear();
-    std::vector<int> last((size_t)nfields, -1);
-    for (const auto& w : waves) {
-        int cur_field = -1, g = -1;
-        for (int i = w.first; i < w.first + w.second; i++) {
-            const int f = items[(size_t)i].field;
-            if (f != cur_field) {
-                g = (int)need.size();
-                need.push_back(0);
-                dep.push_back(last[(size_t)f]);
-                last[(size_t)f] = g;
-                cur_field = f;
-            }
-            grp[(size_t)i] = g;
-            need[(size_t)g]++;
+    const int nf = b.nfields;
+    const double esz = (b.dtype == MGR_F64) ? 8.0 : 4.0;
+    std::vector<double> cost((size_t)nf, 0.0);
+    for (int f = 0; f < nf; f++) {
+        const Plan& p = *b.plans[(size_t)f];
+        for (int k = 0; k < b.kt[(size_t)f]; k++) {
+            const LevelLayout& ly = p.lv[(size_t)k];
+            cost[(size_t)f] += 2.0 * (double)(ly.m[0] * ly.m[1] * ly.m[2]) * esz;
         }
     }
+    for (const auto& w : waves) {
+        int cur = -1;
+        for (int i = w.first; i < w.first + w.second; i++) {
+            const int f = items[(size_t)i].field;
+            if (f != cur) cost[(size_t)f] += 4.0e6;
+            cur = f;
+        }
+    }
+    std::vector<int> byc((size_t)nf);
+    for (int f = 0; f < nf; f++) byc[(size_t)f] = f;
+    std::stable_sort(byc.begin(), byc.end(), [&](int a, int c) { return cost[(size_t)a] > cost[(size_t)c]; });
+    std::vector<double> load((size_t)nq, 0.0);
+    std::vector<int> fq((size_t)nf, 0);
+    for (int f : byc) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        fq[(size_t)f] = q;
+        load[(size_t)q] += cost[(size_t)f];
+    }
+    order.clear();
+    grp.clear();
+    dep.clear();
+    need.clear();
+    start.assign((size_t)nq + 1, 0);
+    std::vector<int> last((size_t)nf, -1);
+    for (int q = 0; q < nq; q++) {
+        start[(size_t)q] = (int)order.size();
+        for (const auto& w : waves) {
+            int cur = -1, g = -1;
+            for (int i = w.first; i < w.first + w.second; i++) {
+                const int f = items[(size_t)i].field;
+                if (fq[(size_t)f] != q) continue;
+                if (f != cur) {
+                    g = (int)need.size();
+                    need.push_back(0);
+                    dep.push_back(last[(size_t)f]);
+                    last[(size_t)f] = g;
+                    cur = f;
+                }
+                order.push_back(i);
+                grp.push_back(g);
+                need[(size_t)g]++;
+            }
+        }
+    }
+    start[(size_t)nq] = (int)order.size();
+}
+
+// XCDs of the current device (queues of the persistent form).
+int device_queue_count()
+{
+    int dev = 0, n = 1;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess)
+        n = 1;
+    return std::min(std::max(n, 1), kMaxQueues);
+}
+
+QueueTables queue_tables(const BatchPlan& b, const int* grp, const int* dep, const int* need, const int* order)
+{
+    QueueTables qt;
+    qt.grp = grp;
+    qt.dep = dep;
+    qt.need = need;
+    qt.order = order;
+    qt.nq = b.nq;
+    for (int q = 0; q <= kMaxQueues; q++) qt.start[q] = b.qstart[(size_t)std::min(q, b.nq)];
+    return qt;
+}
+
+QueueState queue_state(int* words)
+{
+    QueueState qs;
+    qs.abort = words;
+    qs.err = words + 1;
+    qs.next = words + 2;
+    qs.done = words + kQueueWordsFixed;
+    return qs;
 }
 
 template <typename T>
@@ -1767,11 +1844,13 @@ int batch_upload(BatchPlan& b, int chunk)
     b.off_tailf = take(sizeof(int) * t.tailf.size());
     b.off_ptrs = take(2 * sizeof(void*) * (size_t)b.nfields);
     b.off_args = take(sizeof(BatchKernelArgs<T>));
-    batch_groups(t.items, t.waves, b.nfields, b.qgrp, b.qdep, b.qneed);
+    b.nq = device_queue_count();
+    batch_queues(b, t.items, t.waves, b.nq, b.qorder, b.qstart, b.qgrp, b.qdep, b.qneed);
+    b.off_qorder = take(sizeof(int) * b.qorder.size());
     b.off_qgrp = take(sizeof(int) * b.qgrp.size());
     b.off_qdep = take(sizeof(int) * b.qdep.size());
     b.off_qneed = take(sizeof(int) * b.qneed.size());
-    b.off_qwords = take(sizeof(int) * (3 + b.qneed.size()));
+    b.off_qwords = take(sizeof(int) * (kQueueWordsFixed + b.qneed.size()));
     if (b.dev) (void)hipFree(b.dev);
     b.dev = nullptr;
     hipError_t e = hipMalloc(&b.dev, off);
@@ -1799,6 +1878,7 @@ int batch_upload(BatchPlan& b, int chunk)
                  {b.off_tail, t.tail.data(), sizeof(TailArgs<T>) * t.tail.size()},
                  {b.off_tailf, t.tailf.data(), sizeof(int) * t.tailf.size()},
                  {b.off_args, &ka, sizeof(ka)},
+                 {b.off_qorder, b.qorder.data(), sizeof(int) * b.qorder.size()},
                  {b.off_qgrp, b.qgrp.data(), sizeof(int) * b.qgrp.size()},
                  {b.off_qdep, b.qdep.data(), sizeof(int) * b.qdep.size()},
                  {b.off_qneed, b.qneed.data(), sizeof(int) * b.qneed.size()}};
@@ -1810,13 +1890,14 @@ int batch_upload(BatchPlan& b, int chunk)
     // the queue words start cleared (a fresh allocation may hold anything),
     // so that mgr_batch_check reads no stale state before the first
     // persistent run on these tables
-    const std::vector<int> zeros(3 + b.qneed.size(), 0);
+    const std::vector<int> zeros(kQueueWordsFixed + b.qneed.size(), 0);
     e = hipMemcpy(d + b.off_qwords, zeros.data(), sizeof(int) * zeros.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "clear queue words");
     b.waves = t.waves;
     b.n_items = (int)t.items.size();
     b.n_tail = (int)t.tail.size();
     b.chunk = chunk;
+    b.ran_persistent = 0;
     return MGR_OK;
 }
 
@@ -1848,21 +1929,18 @@ int batch_run(BatchPlan& b, const void* const* src, void* const* dst, hipStream_
     }
     const BatchKernelArgs<T>* dev_args = (const BatchKernelArgs<T>*)(d + b.off_args);
     if (b.persistent) {
-        QueueTables qt;
-        qt.grp = (const int*)(d + b.off_qgrp);
-        qt.dep = (const int*)(d + b.off_qdep);
-        qt.need = (const int*)(d + b.off_qneed);
-        qt.total = b.n_items;
-        int* w = (int*)(d + b.off_qwords);
-        QueueState qs;
-        qs.next = w;
-        qs.abort = w + 1;
-        qs.err = w + 2;
-        qs.done = w + 3;
-        const int grid = std::max(1, std::min(b.n_items, batch_queue_slots<T>()));
+        QueueTables qt = queue_tables(b, (const int*)(d + b.off_qgrp), (const int*)(d + b.off_qdep),
+                                      (const int*)(d + b.off_qneed), (const int*)(d + b.off_qorder));
+        QueueState qs = queue_state((int*)(d + b.off_qwords));
+        // one round of resident workgroups whatever the item count: the
+        // device deals workgroups to its XCDs in turn, so every queue has
+        // workgroups (those of an empty queue end at once)
+        const int grid = std::max(b.nq, batch_queue_slots<T>());
+        b.ran_persistent = 1;
         MGR_TRY(timed(KC_BATCH, -1, st,
                       [&] {
-                          return launch_batch_queue<T>(dev_args, qt, qs, 3 + (int)b.qneed.size(), grid, b.poll_limit,
+                          return launch_batch_queue<T>(dev_args, qt, qs, kQueueWordsFixed + (int)b.qneed.size(), grid,
+                                                       b.poll_limit,
                                                        st);
                       }),
                 "batch queue launch");
@@ -1928,20 +2006,27 @@ int batch_create(int nfields, const int* ndim, const int64_t* const* shapes, con
 // The transaction model of a batch configuration (the paper's
 // performance-model pruning of launch shapes, Sec. III-C, applied to the
 // streaming items' tile extent along dimension 0, the chunk of coarse
-// planes): predicted time = a + x * bytes + y * items, with bytes the
-// streaming items' traffic including the 3-plane halo each item re-reads
-// and items the streaming items (each with its start-up and drain).  The
-// constants a, x, y are not guessed: batch_autotune fits them, per launch
-// form, to timed runs of the actual fields.
+// planes): predicted time = a + x * bytes + y * items + z * depth, with
+//   bytes: the streaming items' traffic including the 3-plane halo each item
+//          re-reads (falls as the chunk grows),
+//   items: the streaming items, each with its start-up and drain (falls),
+//   depth: the fine planes the longest streaming item of each level step
+//          streams one after the other, summed over the level steps (grows:
+//          a level step ends with its longest item, however idle the rest
+//          of the device is).
+// The constants are not guessed: batch_autotune fits them, per launch form,
+// to timed runs of the actual fields.
 struct BatchTerms {
-    double bytes = 0.0, items = 0.0;
+    double bytes = 0.0, items = 0.0, depth = 0.0;
 };
 BatchTerms batch_terms(const BatchPlan& b, int chunk)
 {
     BatchTerms t;
     const double esz = (b.dtype == MGR_F64) ? 8.0 : 4.0;
+    std::vector<double> longest;
     for (int f = 0; f < b.nfields; f++) {
         const Plan& p = *b.plans[(size_t)f];
+        if ((int)longest.size() < b.kt[(size_t)f]) longest.resize((size_t)b.kt[(size_t)f], 0.0);
         for (int k = 0; k < b.kt[(size_t)f]; k++) {
             const LevelLayout& ly = p.lv[(size_t)k];
             const double V = (double)(ly.m[0] * ly.m[1] * ly.m[2]);
@@ -1955,49 +2040,80 @@ BatchTerms batch_terms(const BatchPlan& b, int chunk)
             const double halo = act0 ? (2.0 * ch + 3.0) / (2.0 * ch) : 1.0;
             t.bytes += 2.0 * V * esz * halo;
             t.items += tiles * nch;
+            longest[(size_t)k] = std::max(longest[(size_t)k], act0 ? 2.0 * ch + 3.0 : 1.0);
         }
     }
+    for (double d : longest) t.depth += d;
     return t;
 }
 
-// Least-squares fit of time = a + x bytes + y items to measured points
-// (normal equations, 3x3, Cramer's rule); negative slopes (noise) are
-// clamped to zero with the intercept refitted.
-void fit_model(const std::vector<BatchTerms>& t, const std::vector<double>& ms, double m[3])
+// Non-negative least-squares fit of time = a + x bytes + y items + z depth
+// to the measured points: every subset of the four terms is fitted without
+// constraints (normal equations, Gaussian elimination) and the best fit
+// whose coefficients are all non-negative is kept (a negative constant has
+// no physical reading; with as many probes as terms an unconstrained fit
+// would interpolate the noise).
+constexpr int kModelTerms = 4;
+void fit_model(const std::vector<BatchTerms>& t, const std::vector<double>& ms, double m[kModelTerms])
 {
-    double S[3][3] = {{0}}, r[3] = {0};
-    for (size_t i = 0; i < t.size(); i++) {
-        const double v[3] = {1.0, t[i].bytes * 1e-9, t[i].items * 1e-3};  // scaled for conditioning
-        for (int a = 0; a < 3; a++) {
-            r[a] += v[a] * ms[i];
-            for (int c = 0; c < 3; c++) S[a][c] += v[a] * v[c];
-        }
-    }
-    auto det = [](double A[3][3]) {
-        return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
-               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    const double scale[kModelTerms] = {1.0, 1e-9, 1e-3, 1e-2};  // conditioning
+    auto term = [&](size_t i, int c) {
+        const double v[kModelTerms] = {1.0, t[i].bytes, t[i].items, t[i].depth};
+        return v[c] * scale[c];
     };
-    const double D = det(S);
-    double sol[3] = {0, 0, 0};
-    if (std::fabs(D) > 1e-30) {
-        for (int c = 0; c < 3; c++) {
-            double A[3][3];
-            for (int i = 0; i < 3; i++)
-                for (int j = 0; j < 3; j++) A[i][j] = (j == c) ? r[i] : S[i][j];
-            sol[c] = det(A) / D;
+    double best_res = 1e300, best[kModelTerms] = {0, 0, 0, 0};
+    for (int mask = 1; mask < (1 << kModelTerms); mask++) {
+        int idx[kModelTerms], n = 0;
+        for (int c = 0; c < kModelTerms; c++)
+            if (mask & (1 << c)) idx[n++] = c;
+        if ((size_t)n > t.size()) continue;
+        double S[kModelTerms][kModelTerms + 1] = {{0}};
+        for (size_t i = 0; i < t.size(); i++)
+            for (int a = 0; a < n; a++) {
+                for (int c = 0; c < n; c++) S[a][c] += term(i, idx[a]) * term(i, idx[c]);
+                S[a][n] += term(i, idx[a]) * ms[i];
+            }
+        bool ok = true;
+        for (int c = 0; c < n && ok; c++) {  // elimination with partial pivoting
+            int piv = c;
+            for (int r = c + 1; r < n; r++)
+                if (std::fabs(S[r][c]) > std::fabs(S[piv][c])) piv = r;
+            if (std::fabs(S[piv][c]) < 1e-12) {
+                ok = false;
+                break;
+            }
+            for (int j = 0; j <= n; j++) std::swap(S[c][j], S[piv][j]);
+            for (int r = 0; r < n; r++) {
+                if (r == c) continue;
+                const double f = S[r][c] / S[c][c];
+                for (int j = c; j <= n; j++) S[r][j] -= f * S[c][j];
+            }
+        }
+        if (!ok) continue;
+        double sol[kModelTerms] = {0, 0, 0, 0};
+        for (int a = 0; a < n; a++) {
+            sol[idx[a]] = S[a][n] / S[a][a];
+            if (sol[idx[a]] < 0.0) ok = false;
+        }
+        if (!ok) continue;
+        double res = 0.0;
+        for (size_t i = 0; i < t.size(); i++) {
+            double p = 0.0;
+            for (int c = 0; c < kModelTerms; c++) p += sol[c] * term(i, c);
+            res += (p - ms[i]) * (p - ms[i]);
+        }
+        if (res < best_res) {
+            best_res = res;
+            std::copy(sol, sol + kModelTerms, best);
         }
     }
-    sol[1] = std::max(0.0, sol[1]);
-    sol[2] = std::max(0.0, sol[2]);
-    double resid = 0.0;
-    for (size_t i = 0; i < t.size(); i++) resid += ms[i] - sol[1] * t[i].bytes * 1e-9 - sol[2] * t[i].items * 1e-3;
-    sol[0] = t.empty() ? 0.0 : resid / (double)t.size();
-    m[0] = sol[0];
-    m[1] = sol[1] * 1e-9;
-    m[2] = sol[2] * 1e-3;
+    for (int c = 0; c < kModelTerms; c++) m[c] = best[c] * scale[c];
 }
 
-double model_ms(const double m[3], const BatchTerms& t) { return m[0] + m[1] * t.bytes + m[2] * t.items; }
+double model_ms(const double m[kModelTerms], const BatchTerms& t)
+{
+    return m[0] + m[1] * t.bytes + m[2] * t.items + m[3] * t.depth;
+}
 
 // ---- class-packed layout and progressive recomposition --------------------
 // Segment starts of the class-packed layout: class 0 is the level-0 grid,
@@ -2249,7 +2365,7 @@ int run_decompose_noalloc(const void* src, void* dst, int dtype, int ndim, const
 // the item arguments are never used), for the host check of the queue.
 template <typename T>
 int batch_host_items_t(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int chunk,
-                       BatchPlan& b)
+                       int nq, BatchPlan& b)
 {
     char* const base = reinterpret_cast<char*>((uintptr_t)1 << 40);  // stands in for device allocations
     size_t ws_total = 0;
@@ -2274,22 +2390,24 @@ int batch_host_items_t(int nfields, const int* ndim, const int64_t* const* shape
     b.ws = nullptr;
     for (auto& p : b.plans) p->tables = nullptr;
     if (rc) return rc;
-    batch_groups(t.items, t.waves, b.nfields, b.qgrp, b.qdep, b.qneed);
+    b.nq = nq;
+    batch_queues(b, t.items, t.waves, nq, b.qorder, b.qstart, b.qgrp, b.qdep, b.qneed);
     b.waves = t.waves;
     b.n_items = (int)t.items.size();
     return MGR_OK;
 }
 
 int batch_host_items(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int dtype,
-                     int chunk, BatchPlan& b)
+                     int chunk, int nq, BatchPlan& b)
 {
     if (nfields <= 0 || !ndim || !shapes) return fail(MGR_ERR_ARG, "nfields, ndim or shapes invalid");
+    if (nq < 1 || nq > kMaxQueues) return fail(MGR_ERR_ARG, "nqueues must be 1.." + std::to_string(kMaxQueues));
     if (dtype != MGR_F32 && dtype != MGR_F64) return fail(MGR_ERR_ARG, "dtype must be MGR_F32 or MGR_F64");
     if (chunk < 1 || chunk > kMaxBatchChunk) return fail(MGR_ERR_ARG, "chunk must be 1.." + std::to_string(kMaxBatchChunk));
     b.dtype = dtype;
     b.nfields = nfields;
-    return dtype == MGR_F64 ? batch_host_items_t<double>(nfields, ndim, shapes, nlevels, chunk, b)
-                            : batch_host_items_t<float>(nfields, ndim, shapes, nlevels, chunk, b);
+    return dtype == MGR_F64 ? batch_host_items_t<double>(nfields, ndim, shapes, nlevels, chunk, nq, b)
+                            : batch_host_items_t<float>(nfields, ndim, shapes, nlevels, chunk, nq, b);
 }
 
 // Host side of the queue protocol (mgr_queue.h) for mgr_batch_queue_check.
@@ -2307,33 +2425,29 @@ struct HostQueueOps {
 };
 
 // Runs the queue protocol of a plan's item list on nthreads host threads
-// standing in for workgroups; each "runs" an item by checking that its
-// dependency group has finished (a separate sequentially consistent count
-// kept outside the protocol), spinning for a random while, and counting it.
-// The thread that takes stall_item (>= 0) stops there without finishing it,
-// as a workgroup that never completes would.  out: items run, items that
-// started before their dependency group finished, the error word (1 + the
-// item whose wait timed out, or 0), items left untaken.
+// standing in for workgroups (thread t serves queue t mod nq, as the
+// workgroups of a launch are dealt to every XCD); each "runs" an item by
+// checking that its dependency group has finished (a separate sequentially
+// consistent count kept outside the protocol), spinning for a random while,
+// and counting it.  The thread that takes position stall (>= 0) stops there
+// without finishing it, as a workgroup that never completes would.  out:
+// items run, items that started before their dependency group finished, the
+// error word (1 + the position whose wait timed out, or 0), positions left
+// untaken.
 int queue_check(const BatchPlan& b, int nthreads, unsigned limit, int stall_item, uint64_t seed, int64_t* out)
 {
     if (nthreads < 1 || nthreads > 1024) return fail(MGR_ERR_ARG, "nthreads must be 1..1024");
     const int ng = (int)b.qneed.size();
-    std::vector<int> words((size_t)(3 + ng), 0), fin((size_t)ng, 0);
-    QueueTables qt;
-    qt.grp = b.qgrp.data();
-    qt.dep = b.qdep.data();
-    qt.need = b.qneed.data();
-    qt.total = b.n_items;
-    QueueState qs;
-    qs.next = &words[0];
-    qs.abort = &words[1];
-    qs.err = &words[2];
-    qs.done = &words[3];
+    std::vector<int> words((size_t)(kQueueWordsFixed + ng), 0), fin((size_t)ng, 0);
+    const QueueTables qt = queue_tables(b, b.qgrp.data(), b.qdep.data(), b.qneed.data(), b.qorder.data());
+    const QueueState qs = queue_state(words.data());
     std::atomic<int64_t> ran{0}, bad{0};
     auto worker = [&](int tid) {
         uint64_t x = seed * 0x9E3779B97F4A7C15ull + (uint64_t)tid + 1;
+        const int q = tid % b.nq;
+        int last_dg = -1;
         for (;;) {
-            const int i = queue_take(qt, qs, limit, HostQueueOps{});
+            const int i = queue_take(qt, qs, q, limit, last_dg, HostQueueOps{});
             if (i < 0) return;
             const int g = b.qgrp[(size_t)i], dg = b.qdep[(size_t)g];
             if (dg >= 0 && __atomic_load_n(&fin[(size_t)dg], __ATOMIC_SEQ_CST) != b.qneed[(size_t)dg]) bad++;
@@ -2351,10 +2465,13 @@ int queue_check(const BatchPlan& b, int nthreads, unsigned limit, int stall_item
     std::vector<std::thread> th;
     for (int t = 0; t < nthreads; t++) th.emplace_back(worker, t);
     for (auto& t : th) t.join();
+    int64_t untaken = 0;
+    for (int q = 0; q < b.nq; q++)
+        untaken += std::max<int64_t>(0, (int64_t)(b.qstart[(size_t)q + 1] - b.qstart[(size_t)q]) - qs.next[q]);
     out[0] = ran.load();
     out[1] = bad.load();
-    out[2] = words[2];
-    out[3] = std::max<int64_t>(0, (int64_t)b.n_items - (int64_t)words[0]);
+    out[2] = *qs.err;
+    out[3] = untaken;
     return MGR_OK;
 }
 
@@ -2762,7 +2879,7 @@ int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const
         if (capturing(st)) return fail(MGR_ERR_CAPTURE, "autotuning times launches; not during capture");
         if (top_k < 1) top_k = 3;
         const int cand[] = {2, 4, 8, 16, 32, 64, 128};
-        const int probes[] = {2, 16, 128};
+        const int probes[] = {2, 4, 16, 64, 128};
         hipEvent_t e0, e1;
         MGR_TRY(hipEventCreate(&e0), "event");
         MGR_TRY(hipEventCreate(&e1), "event");
@@ -2844,7 +2961,7 @@ int mgr_batch_tuning(const mgr_batch_plan* plan, int* persistent, double* model)
     if (persistent) *persistent = b->persistent;
     if (model)
         for (int m = 0; m < 2; m++)
-            for (int i = 0; i < 3; i++) model[3 * m + i] = b->model[m][i];
+            for (int i = 0; i < kModelTerms; i++) model[kModelTerms * m + i] = b->model[m][i];
     return MGR_OK;
 }
 
@@ -2891,23 +3008,38 @@ int mgr_batch_check(mgr_batch_plan* plan)
         BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
         if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
         MGR_TRY(hipDeviceSynchronize(), "synchronise");
-        std::vector<int> w(3 + b->qneed.size(), 0);
+        std::vector<int> w(kQueueWordsFixed + b->qneed.size(), 0);
         MGR_TRY(hipMemcpy(w.data(), (char*)b->dev + b->off_qwords, sizeof(int) * w.size(), hipMemcpyDeviceToHost),
                 "read queue words");
-        if (w[1] || w[2]) {
+        const QueueState qs = queue_state(w.data());
+        if (*qs.abort || *qs.err) {
             std::string d;
-            const int item = w[2] - 1;
-            if (item >= 0 && item < b->n_items) {
-                const int g = b->qgrp[(size_t)item], dg = b->qdep[(size_t)g];
-                d = " (group " + std::to_string(g) + ", waiting on group " + std::to_string(dg);
+            const int pos = *qs.err - 1;
+            int item = -1;
+            if (pos >= 0 && pos < (int)b->qorder.size()) {
+                item = b->qorder[(size_t)pos];
+                int q = 0;
+                while (q + 1 < b->nq && b->qstart[(size_t)q + 1] <= pos) q++;
+                const int g = b->qgrp[(size_t)pos], dg = b->qdep[(size_t)g];
+                d = " (queue " + std::to_string(q) + ", group " + std::to_string(g) + ", waiting on group " +
+                    std::to_string(dg);
                 if (dg >= 0)
-                    d += " with " + std::to_string(w[3 + (size_t)dg]) + " of " + std::to_string(b->qneed[(size_t)dg]) +
+                    d += " with " + std::to_string(qs.done[dg]) + " of " + std::to_string(b->qneed[(size_t)dg]) +
                          " items finished";
-                d += "; " + std::to_string(w[0]) + " of " + std::to_string(b->n_items) + " items taken)";
+                d += "; " + std::to_string(std::min(qs.next[q], b->qstart[(size_t)q + 1] - b->qstart[(size_t)q])) +
+                     " of the queue's " + std::to_string(b->qstart[(size_t)q + 1] - b->qstart[(size_t)q]) +
+                     " items taken)";
             }
             return fail(MGR_ERR_HIP, "persistent batch: a dependency wait timed out at work item " +
                                          std::to_string(item) + d + "; the outputs of that run are incomplete");
         }
+        if (b->ran_persistent)
+            for (int q = 0; q < b->nq; q++)
+                if (qs.next[q] < b->qstart[(size_t)q + 1] - b->qstart[(size_t)q])
+                    return fail(MGR_ERR_HIP, "persistent batch: queue " + std::to_string(q) + " has items no workgroup took (" +
+                                                 std::to_string(qs.next[q]) + " of " +
+                                                 std::to_string(b->qstart[(size_t)q + 1] - b->qstart[(size_t)q]) +
+                                                 "); the outputs of that run are incomplete");
         return MGR_OK;
     } catch (...) {
         return fail(MGR_ERR_HIP, "unexpected exception");
@@ -2915,13 +3047,14 @@ int mgr_batch_check(mgr_batch_plan* plan)
 }
 
 int mgr_batch_queue_check(int nfields, const int* ndim, const int64_t* const* shapes, const int* nlevels, int dtype,
-                          int chunk, int nthreads, unsigned poll_limit, int stall_item, uint64_t seed, int64_t* out)
+                          int chunk, int nqueues, int nthreads, unsigned poll_limit, int stall_item, uint64_t seed,
+                          int64_t* out)
 {
     try {
         g_err.clear();
         if (!out) return fail(MGR_ERR_ARG, "out is NULL");
         BatchPlan b;
-        int rc = batch_host_items(nfields, ndim, shapes, nlevels, dtype, chunk, b);
+        int rc = batch_host_items(nfields, ndim, shapes, nlevels, dtype, chunk, nqueues, b);
         if (rc) return rc;
         return queue_check(b, nthreads, poll_limit ? poll_limit : (1u << 20), stall_item, seed, out);
     } catch (const std::bad_alloc&) {

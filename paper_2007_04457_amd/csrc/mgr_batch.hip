@@ -155,8 +155,15 @@ k_batch(const BatchKernelArgs<T>* __restrict__ A, int first)
 // Device side of the queue protocol (mgr_queue.h), run by a whole wave:
 // every value it returns is wave-uniform (one lane does each atomic and the
 // result is broadcast), so the loops and branches around it are uniform.
-// Agent-scope atomics; polls are relaxed loads (no cache invalidation) with a
-// sleep between them.
+// The queue words are accessed with agent-scope atomics; polls are relaxed
+// loads with a sleep between them.  An item and the items it depends on run
+// on one XCD, under one L2: the producer's stores have reached that L2 when
+// its counter moves (the caller waits for them), so no L2 write-back is
+// needed.  The consumer must still drop its CU's L1, which may hold lines it
+// read before the producer wrote them (a cache line can span the parts of
+// two items); on this device only an agent-scope invalidation reaches the L1
+// of a workgroup whose waves share one CU (a workgroup-scope one is a no-op
+// there), and it also drops the XCD's clean L2 lines, never dirty ones.
 struct DevQueueOps {
     __device__ static bool leader() { return (threadIdx.x & 63) == 0; }
     __device__ int load_relaxed(int* p) const
@@ -170,11 +177,10 @@ struct DevQueueOps {
         if (leader()) r = __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return __builtin_amdgcn_readfirstlane(r);
     }
-    // release at agent scope (one write-back of this XCD's L2), waited for
-    // explicitly before the counter moves
+    // the caller has waited until every store of the item reached the L2
     __device__ void add_release(int* p, int v) const
     {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         if (leader()) (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -205,35 +211,39 @@ __device__ __forceinline__ void run_item(const BatchKernelArgs<T>* A, const Batc
     }
 }
 
-// The persistent form: every workgroup takes items from the queue until it
-// is empty (or the run is aborted), waiting for each item's dependency
-// group first.  The grid size is free (a workgroup takes an item only while
-// it runs).  Wave 0 takes and finishes items as a whole wave (the branch on
-// the wave index is uniform); the item index is broadcast through LDS and
-// read back as a uniform value, so the loop's exit and every branch around
-// its barriers are uniform: with a per-thread index the compiler may
-// restructure the loop so that the lanes of one wave take different paths
-// around a barrier, and the wave never reconverges.  After an item every
-// thread waits until its own memory operations have completed (its stores
-// are then in the L2), the barrier then lets wave 0 release them at agent
-// scope with one write-back of the L2 before it marks the item finished;
-// wave 0's acquire after the wait precedes the barrier that starts the next
-// item for every thread.
+// The persistent form: every workgroup takes items from the queue of the XCD
+// it runs on until that queue is empty (or the run is aborted), waiting for
+// each item's dependency group first.  The grid size is free (a workgroup
+// takes an item only while it runs; workgroups are dealt to every XCD).
+// Wave 0 takes and finishes items as a whole wave (the branch on the wave
+// index is uniform); the position is broadcast through LDS and read back as
+// a uniform value, so the loop's exit and every branch around its barriers
+// are uniform: with a per-thread index the compiler may restructure the loop
+// so that the lanes of one wave take different paths around a barrier, and
+// the wave never reconverges.  After an item every thread waits until its
+// own memory operations have completed (its stores are then in the L2), the
+// barrier then lets wave 0 mark the item finished; wave 0's cache
+// invalidation after the wait precedes the barrier that starts the next item
+// for every thread (all waves of a workgroup share one CU and its L1).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_batch_queue(const BatchKernelArgs<T>* __restrict__ A, QueueTables qt, QueueState qs, unsigned limit)
 {
     __shared__ int s_item;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    unsigned xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    const int q = (int)(xcc & 0xfu) % qt.nq;
+    int last_dg = -1;  // wave 0's
     for (;;) {
         if (wave == 0) {
-            const int t = queue_take(qt, qs, limit, DevQueueOps{});
+            const int t = queue_take(qt, qs, q, limit, last_dg, DevQueueOps{});
             if (DevQueueOps::leader()) s_item = t;
         }
         __syncthreads();
         const int i = __builtin_amdgcn_readfirstlane(s_item);
         if (i < 0) break;
-        run_item(A, A->items + i);
+        run_item(A, A->items + qt.order[i]);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no memory operation moves below the wait
         __builtin_amdgcn_s_waitcnt(0);             // this wave's loads and stores completed
         __syncthreads();
@@ -292,7 +302,7 @@ template <typename T>
 hipError_t launch_batch_queue(const BatchKernelArgs<T>* dev_a, const QueueTables& qt, const QueueState& qs, int words,
                               int grid, unsigned limit, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min(64, (words + 255) / 256)), dim3(256), 0, st, qs.next,
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min(64, (words + 255) / 256)), dim3(256), 0, st, qs.abort,
                        words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
