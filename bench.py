@@ -289,17 +289,22 @@ def other_workloads(mgr, torch, synth, steps, warmup):
             rec()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t_host = 0.0
         for _ in range(steps):
+            h0 = time.perf_counter()
             dec()
             rec()
+            t_host += time.perf_counter() - h0
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
         td = event_ms(torch, dec)
         tr = event_ms(torch, rec)
+        ts = event_ms(torch, lambda: (dec(), rec()))
         err = float((r - x).abs().max().item() / x.abs().max().item())
         n = x.numel()
         out[name] = {"GBps": round(2 * n * s / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 4),
                      "t_decompose_ms": round(td, 4), "t_recompose_ms": round(tr, 4),
+                     "event_ms_per_step": round(ts, 4), "host_enqueue_ms_per_step": round(t_host / steps * 1e3, 4),
                      "roundtrip_max_rel_err": err}
         del x, y, r
         torch.cuda.empty_cache()

@@ -247,19 +247,6 @@ void mgr_finalize(void);
  * previous value.  Process-wide; affects calls enqueued afterwards. */
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes);
 
-/* Workgroup slots per compute unit that the recomposition's finest-level
- * streaming launch leaves free.  The recomposition computes the finest
- * level step's correction on one stream while the coarser level steps run
- * on others; the finest streaming launch is sized to the device's resident
- * capacity, so without free slots the small launches of the coarser levels
- * wait for its workgroups.  A tuning knob: on the MI355X at 513^3 a value of
- * 4 shortens the FP32 recomposition by about 3% and lengthens the FP64 one
- * by about 6% (the coarser launches then mostly wait on memory, not on
- * slots).  Clamped to 0..8; default 0.  Returns the previous value.
- * Process-wide; affects calls enqueued afterwards; results do not depend on
- * it. */
-int mgr_set_recompose_reserve(int slots);
-
 /* ---- batched decomposition ----------------------------------------------
  * Many independent fields (any mix of shapes, dimensionalities, coordinates
  * and level counts, one dtype) decomposed together: every workgroup-sized

@@ -22,7 +22,6 @@ __all__ = [
     "mgr_decompose", "mgr_recompose", "mgr_decompose_adjoint", "mgr_recompose_adjoint",
     "mgr_decompose_noalloc", "mgr_prepare",
     "mgr_class_map", "class_masks", "mgr_max_levels", "mgr_bench_copy", "mgr_finalize", "mgr_set_tail_max_nodes",
-    "mgr_set_recompose_reserve",
     "mgr_timing_enable", "mgr_timing_disable", "mgr_timing_read", "mgr_kernel_name",
     "decompose", "recompose", "decompose_adjoint", "recompose_adjoint", "Decompose", "Recompose",
     "kernel_classes", "BatchPlan", "batch_queue_check",
@@ -292,13 +291,6 @@ def mgr_set_tail_max_nodes(max_nodes):
     """Level steps with at most max_nodes nodes share one launch; returns
     the previous setting (0 disables)."""
     return _lib.load().mgr_set_tail_max_nodes(int(max_nodes))
-
-
-def mgr_set_recompose_reserve(slots):
-    """Workgroup slots per CU the recomposition's finest correction leaves
-    free for the coarser levels running alongside; returns the previous
-    setting."""
-    return _lib.load().mgr_set_recompose_reserve(int(slots))
 
 
 def mgr_finalize():

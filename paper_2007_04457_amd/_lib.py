@@ -71,8 +71,6 @@ def load():
     lib.mgr_finalize.restype = None
     lib.mgr_set_tail_max_nodes.argtypes = [ctypes.c_int64]
     lib.mgr_set_tail_max_nodes.restype = ctypes.c_int64
-    lib.mgr_set_recompose_reserve.argtypes = [ctypes.c_int]
-    lib.mgr_set_recompose_reserve.restype = ctypes.c_int
     lib.mgr_bench_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.mgr_bench_copy.restype = ctypes.c_int
     lib.mgr_timing_enable.argtypes = [ctypes.c_int, ctypes.c_int]

@@ -659,7 +659,7 @@ T* corr(const Plan& p, int k, void* ws = nullptr)
 // vector goes to corr(k).
 template <typename T>
 int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 av, T* C, View3 cv,
-                 T* W, bool write_coarse, hipStream_t st, T* Fout = nullptr, int reserve = 0)
+                 T* W, bool write_coarse, hipStream_t st, T* Fout = nullptr)
 {
     const LevelLayout& ly = p.lv[(size_t)k];
     StreamArgs<T> a;
@@ -676,7 +676,7 @@ int stream_level(const Plan& p, int k, bool dec, const T* A, const T* Z, View3 a
     a.write_coarse = write_coarse ? 1 : 0;
     a.chunk = a.nt1 = a.nt2 = a.nch = 0;
     MGR_TRY(timed(dec ? KC_STREAM_DEC : KC_STREAM_LOAD, k, st,
-                  [&] { return launch_stream_level<T>(a, dec, st, reserve); }),
+                  [&] { return launch_stream_level<T>(a, dec, st); }),
             "level kernel launch");
     return MGR_OK;
 }
@@ -852,13 +852,15 @@ int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     return MGR_OK;
 }
 
-// Two more streams per device for the recomposition's corrections (default
-// priority): one for the finest level step, one for the coarser ones, with
-// one event per level step; the enqueueing is serialised.
+// Three more streams per device for the recomposition (default priority,
+// non-blocking): s0 for the finest level step's correction, s for the
+// coarser ones, sr for the tail and the coarser interpolations; one event per
+// level step (correction done), one for the coarser interpolations and the
+// fork.  The enqueueing is serialised.
 constexpr int kMaxLevels = 64;  // above any level count of an int64 extent
 struct AuxStream {
-    hipStream_t s = nullptr, s0 = nullptr;
-    hipEvent_t start = nullptr;
+    hipStream_t s = nullptr, s0 = nullptr, sr = nullptr;
+    hipEvent_t start = nullptr, rdone = nullptr;
     hipEvent_t done[kMaxLevels] = {};
 };
 std::mutex g_aux_mu;
@@ -869,8 +871,10 @@ void destroy_aux(AuxStream& a)
     for (hipEvent_t& ev : a.done)
         if (ev) (void)hipEventDestroy(ev);
     if (a.start) (void)hipEventDestroy(a.start);
+    if (a.rdone) (void)hipEventDestroy(a.rdone);
     if (a.s) (void)hipStreamDestroy(a.s);
     if (a.s0) (void)hipStreamDestroy(a.s0);
+    if (a.sr) (void)hipStreamDestroy(a.sr);
     a = AuxStream{};
 }
 
@@ -885,8 +889,10 @@ hipError_t aux_stream(AuxStream** out)
         // built aside and kept only when complete
         AuxStream n;
         e = hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.sr, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.s0, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&n.start, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.rdone, hipEventDisableTiming);
         for (int k = 0; k < kMaxLevels && e == hipSuccess; k++)
             e = hipEventCreateWithFlags(&n.done[k], hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -907,22 +913,17 @@ bool aux_ready()
     return g_aux[dev].s != nullptr;
 }
 
-// Workgroup slots per CU that the recomposition's finest streaming launch
-// (sized to the resident capacity) leaves free for the coarse levels running
-// alongside it (mgr_set_recompose_reserve).
-std::atomic<int> g_rec_reserve{0};
-
 // Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
 // The correction z_k of every level step depends on the stored coefficients
-// alone (its load vector is formed from them), so they are computed on two
-// more streams (the finest level step on one, the coarser ones, coarsest
-// first, on the other) while the caller's stream runs the coarsest levels
-// and the interpolations, each waiting only for its own z_k: the
-// latency-bound small levels overlap the bandwidth-bound finest ones.  The
-// tail is enqueued first, the finest correction's streaming launch leaves
-// some workgroup slots on every CU free, and the coarser corrections use no
-// whole-CU workgroup, so that the chain of small launches is not held back
-// behind the finest correction's long-lived workgroups.
+// alone (its load vector is formed from them), so they are all independent
+// of the coarse-to-fine chain.  Forked from the caller's stream: s0 computes
+// the finest level step's correction, s the coarser ones (coarsest first), sr
+// runs the tail and the coarser interpolations, each waiting only for its own
+// z_k; the caller's stream joins them and runs the finest interpolation.  The
+// latency-bound small levels thus overlap the bandwidth-bound finest
+// correction; the coarser corrections use no whole-CU workgroup (such a
+// workgroup waits until one CU has drained completely of the finest
+// correction's long-lived workgroups).
 template <typename T>
 int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
@@ -934,33 +935,34 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     const int kt = tail_start(p);
     std::unique_lock<std::mutex> lk(g_aux_mu);
     AuxStream* aux = nullptr;
+    hipStream_t sc = st;  // the stream of the tail and the coarser interpolations
     if (kt > 0) {
         if (!aux_ready() && capturing(st))
             return fail(MGR_ERR_CAPTURE, "auxiliary streams not created and the stream is capturing; call mgr_prepare first");
         MGR_TRY(aux_stream(&aux), "auxiliary stream");
         MGR_TRY(hipEventRecord(aux->start, st), "fork event");
+        MGR_TRY(hipStreamWaitEvent(aux->sr, aux->start, 0), "fork wait");
+        sc = aux->sr;
     }
     if (kt < L) {
         TailArgs<T> a = tail_args<T>(p, kt, src, dst);
         a.Z0 = nullptr;
-        MGR_TRY(timed(KC_TAIL, kt, st, [&] { return launch_tail<T>(a, false, st); }), "tail launch");
+        MGR_TRY(timed(KC_TAIL, kt, sc, [&] { return launch_tail<T>(a, false, sc); }), "tail launch");
     } else {
         View3 cl = level_view(p, L);
-        MGR_TRY(timed(KC_COPY_VIEW, L, st,
-                      [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), st); }),
+        MGR_TRY(timed(KC_COPY_VIEW, L, sc,
+                      [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), sc); }),
                 "coarsest gather");
     }
     if (kt > 0) {
         MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
         if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
-        const int reserve = g_rec_reserve.load();
         for (int i = 0; i < kt; i++) {
             const int k = (i == 0) ? 0 : kt - i;  // finest first (own stream), then coarsest first
             hipStream_t sk = (k == 0) ? aux->s0 : aux->s;
             View3 cv = level_view(p, k);
             T* z = ws + p.Zrec[(size_t)k];
-            const int rsv = (k == 0 && kt > 1) ? reserve : 0;
-            int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z, rsv);
+            int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z);
             if (rc) return rc;
             rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, k == 0);
             if (rc) return rc;
@@ -970,7 +972,13 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
         View3 cv = level_view(p, k);
-        MGR_TRY(hipStreamWaitEvent(st, aux->done[k], 0), "level wait");
+        hipStream_t sk = (k == 0) ? st : sc;
+        if (k == 0) {
+            // join: the coarser interpolations (sr) and the finest correction
+            MGR_TRY(hipEventRecord(aux->rdone, sc), "join event");
+            MGR_TRY(hipStreamWaitEvent(st, aux->rdone, 0), "join wait");
+        }
+        MGR_TRY(hipStreamWaitEvent(sk, aux->done[k], 0), "level wait");
         StreamArgs<T> a;
         a.A = src;
         a.Z = ws + p.Zrec[(size_t)k];
@@ -984,7 +992,7 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
         a.tb = tables_of<T>(p, k);
         a.write_coarse = 0;
         a.chunk = a.nt1 = a.nt2 = a.nch = 0;
-        MGR_TRY(timed(KC_INTERP, k, st, [&] { return launch_stream_recon<T>(a, st); }),
+        MGR_TRY(timed(KC_INTERP, k, sk, [&] { return launch_stream_recon<T>(a, sk); }),
                 "interpolation launch");
     }
     return MGR_OK;
@@ -2763,11 +2771,6 @@ void mgr_finalize(void)
     }
     g_tm.ev.clear();
     g_tm.on = false;
-}
-
-int mgr_set_recompose_reserve(int slots)
-{
-    return g_rec_reserve.exchange(std::min(std::max(slots, 0), 8));
 }
 
 int64_t mgr_set_tail_max_nodes(int64_t max_nodes)

@@ -134,10 +134,8 @@ template <typename T>
 hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, const T* const* src, T* const* dst,
                              int n, bool decompose, hipStream_t st);
 
-// reserve: workgroup slots per CU that the launch (sized to the resident
-// capacity) leaves free, for kernels on other streams that run alongside.
 template <typename T>
-hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st, int reserve = 0);
+hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
 // One adjoint level step (mgr_adjoint.hip): g / gv the input at the level
 // grid's fine nodes, y the solved corrections and G the coarse-node input
 // (packed coarse grid yv), O / ov the level-grid output (not overlapping g).

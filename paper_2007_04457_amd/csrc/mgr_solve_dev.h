@@ -162,16 +162,16 @@ struct RowsSmem {
 // staging, the segment tables, the solve in LDS, and the span's stores.
 template <typename T, int kSpan>
 __device__ __forceinline__ void rows_load(const T* __restrict__ F, int64_t row0, int span, int n,
-                                          T (&tmp)[(kSpan + kBlk - 1) / kBlk])
+                                          T (&tmp)[(kSpan + kBlk - 1) / kBlk], int tid)
 {
     // one descriptor over the span (past its end the loads read zero), one
-    // 32-bit offset per load
-    // (the q-th load's distance from the first goes into the scalar offset,
-    // so the lanes keep one address register for all of them)
+    // 32-bit offset per load; the whole offset is in the per-lane operand,
+    // which is what the hardware range check covers (the instruction's
+    // scalar offset is added after the check)
     const __amdgpu_buffer_rsrc_t r = make_rsrc(F + row0 * n, (unsigned)span * (unsigned)sizeof(T));
-    const unsigned o = threadIdx.x * (unsigned)sizeof(T);
+    const unsigned o = (unsigned)tid * (unsigned)sizeof(T);
 #pragma unroll
-    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) tmp[q] = buf_load_so<T>(r, o, (unsigned)(q * kBlk * sizeof(T)));
+    for (int q = 0; q < (kSpan + kBlk - 1) / kBlk; q++) tmp[q] = buf_load<T>(r, o + (unsigned)(q * kBlk * sizeof(T)));
 }
 
 template <typename T, int kSpan, bool kLdsTab>
@@ -284,13 +284,38 @@ __device__ __forceinline__ void solve_rows_tile(T* __restrict__ F, const FibreMa
     const int span = nrows * n;
     {
         T tmp[(kSpan + kBlk - 1) / kBlk];
-        rows_load<T, kSpan>(F, row0, span, n, tmp);
+        rows_load<T, kSpan>(F, row0, span, n, tmp, (int)threadIdx.x);
         rows_stage<T, kSpan, kLdsTab>(tmp, span, sm);
     }
     rows_tables(m, tb, sm);
     __syncthreads();
     rows_solve_lds<T, kSpan, kLdsTab>(m, tb, nrows, sm, (int)threadIdx.x);
     rows_store(F, row0, span, n, sm);
+}
+
+// The span's stores with their LDS reads issued in batches (a loop of single
+// read-then-store steps waits a full LDS round trip per element): one
+// descriptor over the span, past whose end the stores are dropped, so the
+// unrolled batches need no per-element branch; element indices past the span
+// read its last element instead.
+template <typename T, int kSpan, bool kLdsTab>
+__device__ __forceinline__ void rows_store_batched(T* __restrict__ F, int64_t row0, int span, int n,
+                                                   const RowsSmem<T, kSpan, kLdsTab>& sm, int tid)
+{
+    constexpr int NQ = (kSpan + kBlk - 1) / kBlk;
+    constexpr int CH = (sizeof(T) == 4) ? 11 : 9;  // values in flight per lane
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(F + row0 * n, (unsigned)span * (unsigned)sizeof(T));
+    const unsigned o = (unsigned)tid * (unsigned)sizeof(T);
+#pragma unroll
+    for (int q0 = 0; q0 < NQ; q0 += CH) {
+        T v[CH];
+#pragma unroll
+        for (int q = 0; q < CH; q++)
+            if (q0 + q < NQ) v[q] = sm.f[padded(min((q0 + q) * kBlk + tid, span - 1))];
+#pragma unroll
+        for (int q = 0; q < CH; q++)
+            if (q0 + q < NQ) buf_store(v[q], r, o + (unsigned)((q0 + q) * kBlk * sizeof(T)));
+    }
 }
 
 // The per-level launch: each workgroup runs blocks blockIdx.x, + gridDim.x,
@@ -311,17 +336,20 @@ __device__ __forceinline__ void solve_rows_loop(T* __restrict__ F, const FibreMa
     rows_tables(m, tb, sm);
     T tmp[(kSpan + kBlk - 1) / kBlk];
     int64_t b = blockIdx.x;
-    rows_load<T, kSpan>(F, b < nblk ? b * rpb : 0, span_of(b), n, tmp);
+    rows_load<T, kSpan>(F, b < nblk ? b * rpb : 0, span_of(b), n, tmp, (int)threadIdx.x);
     for (; b < nblk; b += gridDim.x) {
         const int span = span_of(b);
         rows_stage<T, kSpan, kLdsTab>(tmp, span, sm);
-        const int64_t bn = b + gridDim.x;
-        rows_load<T, kSpan>(F, bn < nblk ? bn * rpb : 0, span_of(bn), n, tmp);
-        __syncthreads();
+        // an opaque copy of the thread index: the per-load and per-slot
+        // offsets derived from it are then formed inside the loop rather than
+        // hoisted out of it and held in registers for its whole length
         int tid = (int)threadIdx.x;
         asm volatile("" : "+v"(tid));
+        const int64_t bn = b + gridDim.x;
+        rows_load<T, kSpan>(F, bn < nblk ? bn * rpb : 0, span_of(bn), n, tmp, tid);
+        __syncthreads();
         rows_solve_lds<T, kSpan, kLdsTab>(m, tb, span / n, sm, tid);
-        rows_store(F, b * rpb, span, n, sm);
+        rows_store_batched<T, kSpan, kLdsTab>(F, b * rpb, span, n, sm, tid);
         __syncthreads();  // every lane has read sm.f before the next block is staged
     }
 }

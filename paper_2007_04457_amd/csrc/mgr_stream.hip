@@ -39,7 +39,7 @@ k_stream_level(StreamArgs<T> a)
 }
 
 template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
-hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st, int reserve)
+hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st)
 {
     using G = LevelGeom<kAct1, cols_per_lane<T>()>;
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
@@ -52,7 +52,7 @@ hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st, int reserve)
         // One round of resident workgroups: a second, partial round would
         // run latency-bound on a mostly idle chip.
         static int occ = 0;
-        const int slots = std::max(1, resident_per_cu(kern, occ) - reserve) * device_cu_count();
+        const int slots = resident_per_cu(kern, occ) * device_cu_count();
         const int nch = std::max(1, slots / tiles);
         chunk = (c0 + nch - 1) / nch;
         chunk = std::min(std::max(chunk, 2), kMaxChunk);
@@ -64,22 +64,22 @@ hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st, int reserve)
 }
 
 template <typename T, bool kAct0, bool kAct1, bool kU>
-hipError_t launch_cfg_u(StreamArgs<T> a, bool dec, hipStream_t st, int reserve)
+hipError_t launch_cfg_u(StreamArgs<T> a, bool dec, hipStream_t st)
 {
-    if (dec && a.Z) return launch_level_cfg<T, kAct0, kAct1, true, true, kU>(a, st, reserve);
-    if (dec) return launch_level_cfg<T, kAct0, kAct1, true, false, kU>(a, st, reserve);
-    return launch_level_cfg<T, kAct0, kAct1, false, false, kU>(a, st, reserve);
+    if (dec && a.Z) return launch_level_cfg<T, kAct0, kAct1, true, true, kU>(a, st);
+    if (dec) return launch_level_cfg<T, kAct0, kAct1, true, false, kU>(a, st);
+    return launch_level_cfg<T, kAct0, kAct1, false, false, kU>(a, st);
 }
 
 template <typename T, bool kAct0, bool kAct1>
-hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st, int reserve)
+hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
 {
     // unit column stride of the input and (decomposing) of the coefficients:
     // FP32 column pairs then move in single 8-byte accesses
     const bool unit = a.av.s[2] == 1 && (!dec || a.cv.s[2] == 1);
     if constexpr (cols_per_lane<T>() == 2)
-        if (unit) return launch_cfg_u<T, kAct0, kAct1, true>(a, dec, st, reserve);
-    return launch_cfg_u<T, kAct0, kAct1, false>(a, dec, st, reserve);
+        if (unit) return launch_cfg_u<T, kAct0, kAct1, true>(a, dec, st);
+    return launch_cfg_u<T, kAct0, kAct1, false>(a, dec, st);
 }
 
 }  // namespace
@@ -98,16 +98,16 @@ void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2)
 }
 
 template <typename T>
-hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st, int reserve)
+hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st)
 {
     const bool act0 = a.av.n[0] > 1, act1 = a.av.n[1] > 1;
-    if (act0 && act1) return launch_cfg<T, true, true>(a, dec, st, reserve);
-    if (act0) return launch_cfg<T, true, false>(a, dec, st, reserve);
-    if (!act1) return launch_cfg<T, false, false>(a, dec, st, reserve);
+    if (act0 && act1) return launch_cfg<T, true, true>(a, dec, st);
+    if (act0) return launch_cfg<T, true, false>(a, dec, st);
+    if (!act1) return launch_cfg<T, false, false>(a, dec, st);
     return hipErrorInvalidValue;  // (1, m1, m2) is never formed by the driver
 }
 
-template hipError_t launch_stream_level<float>(StreamArgs<float>, bool, hipStream_t, int);
-template hipError_t launch_stream_level<double>(StreamArgs<double>, bool, hipStream_t, int);
+template hipError_t launch_stream_level<float>(StreamArgs<float>, bool, hipStream_t);
+template hipError_t launch_stream_level<double>(StreamArgs<double>, bool, hipStream_t);
 
 }  // namespace mgr

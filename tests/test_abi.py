@@ -192,3 +192,4 @@ def test_quant_argument_errors(lib):
     out = np.zeros(4)
     assert lib.mgr_quant_bins(2, 3, -1.0, out.ctypes.data_as(dp)) == 1
     assert lib.mgr_quant_bins(4, 3, 1.0, out.ctypes.data_as(dp)) == 1
+
