@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="sinusoid field only, no other workloads")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 96-field batch against serial calls (for profiling it); prints its own JSON")
     ap.add_argument("--dtypes", default="f32,f64", help="comma-separated subset of f32,f64 (default both; "
                                                         "--quick alone means f32)")
     return ap.parse_args()
@@ -370,6 +372,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.batched_only:
+        print(json.dumps({"batched": batched_vs_serial(mgr, torch, synth)}), flush=True)
+        return
     N = int(np.prod(SHAPE))
     L = mgr.mgr_max_levels(SHAPE)
 

@@ -49,12 +49,33 @@ k_solve_strided_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb)
 // after the other with the next block's loads in flight; a block's data are
 // one contiguous span of F, staged through LDS with one pad element per 32
 // so that each lane's segment reads are bank-conflict free.
-template <typename T, bool kLdsTab>
+template <typename T, int kSpan, bool kLdsTab>
 __global__ void __launch_bounds__(kBlk)
 k_solve_rows_wg(T* __restrict__ F, FibreMap m, SolveTables<T> tb, int rows_per_block)
 {
-    __shared__ RowsSmem<T, rows_span<T>(), kLdsTab> sm;
-    solve_rows_loop<T, rows_span<T>(), kLdsTab>(F, m, tb, rows_per_block, sm);
+    __shared__ RowsSmem<T, kSpan, kLdsTab> sm;
+    solve_rows_loop<T, kSpan, kLdsTab>(F, m, tb, rows_per_block, sm);
+}
+
+// Rows launch with a span of kSpan elements per block.
+template <typename T, int kSpan>
+hipError_t launch_rows(T* F, const FibreMap& m, const SolveTables<T>& tb, hipStream_t st)
+{
+    // rows per block: as many as fit, but at most an even share of two
+    // workgroups per CU, so that small levels still spread over the chip
+    const int64_t share = (m.nfib + 2 * (int64_t)device_cu_count() - 1) / (2 * (int64_t)device_cu_count());
+    const int rpb = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(kBlk / m.S), (int64_t)(kSpan / m.n), share}));
+    const int64_t nb = (m.nfib + rpb - 1) / rpb;
+    // one round of resident workgroups, each looping over blocks
+    static int occ_t = 0, occ_g = 0;
+    const int res = (m.S <= kMaxSegWG) ? rows_resident(k_solve_rows_wg<T, kSpan, true>, occ_t)
+                                       : rows_resident(k_solve_rows_wg<T, kSpan, false>, occ_g);
+    const unsigned grid = (unsigned)std::min<int64_t>(nb, (int64_t)res * device_cu_count());
+    if (m.S <= kMaxSegWG)
+        hipLaunchKernelGGL((k_solve_rows_wg<T, kSpan, true>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
+    else
+        hipLaunchKernelGGL((k_solve_rows_wg<T, kSpan, false>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
+    return hipGetLastError();
 }
 
 // Workgroups of the rows kernel one CU holds (cached per kernel).
@@ -186,21 +207,16 @@ hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, So
     m.nfib = m.inner * m.outer;
     m.S = tb.S;
     if (m.inner == 1 && m.S <= kBlk && m.n <= rows_span<T>()) {
-        // rows per block: as many as fit, but at most an even share of two
-        // workgroups per CU, so that small levels still spread over the chip
-        const int64_t share = (m.nfib + 2 * (int64_t)device_cu_count() - 1) / (2 * (int64_t)device_cu_count());
-        const int rpb = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(kBlk / m.S), (int64_t)(rows_span<T>() / m.n), share}));
-        const int64_t nb = (m.nfib + rpb - 1) / rpb;
-        // one round of resident workgroups, each looping over blocks
-        static int occ_t = 0, occ_g = 0;
-        const int res = (m.S <= kMaxSegWG) ? rows_resident(k_solve_rows_wg<T, true>, occ_t)
-                                           : rows_resident(k_solve_rows_wg<T, false>, occ_g);
-        const unsigned grid = (unsigned)std::min<int64_t>(nb, (int64_t)res * device_cu_count());
-        if (m.S <= kMaxSegWG)
-            hipLaunchKernelGGL((k_solve_rows_wg<T, true>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
-        else
-            hipLaunchKernelGGL((k_solve_rows_wg<T, false>), dim3(grid), dim3(kBlk), 0, st, F, m, tb, rpb);
-        return hipGetLastError();
+        // FP64 rows of up to an eighth of the half span take the half-span
+        // kernel: half the LDS and registers per workgroup, three resident
+        // workgroups per CU instead of two, blocks still of eight rows or
+        // more (level 0 of 513^3: 67.6 -> 57.8 us).  In FP32 the full span
+        // already holds three, and halving it measured slower (41.0 -> 47.6).
+        if constexpr (sizeof(T) == 8) {
+            constexpr int kHalf = rows_span<T>() / 2;
+            if (m.n * 8 <= kHalf) return launch_rows<T, kHalf>(F, m, tb, st);
+        }
+        return launch_rows<T, rows_span<T>()>(F, m, tb, st);
     }
     if (m.inner > 1 && m.S <= kMaxSegWG) {
         hipLaunchKernelGGL(k_solve_strided_wg<T>, dim3((unsigned)((m.nfib + 63) / 64)), dim3(64, m.S), 0, st,
