@@ -207,15 +207,6 @@ hipError_t launch_solve_fibres(T* F, int64_t n, int64_t inner, int64_t outer, So
     m.nfib = m.inner * m.outer;
     m.S = tb.S;
     if (m.inner == 1 && m.S <= kBlk && m.n <= rows_span<T>()) {
-        // FP64 rows of up to an eighth of the half span take the half-span
-        // kernel: half the LDS and registers per workgroup, three resident
-        // workgroups per CU instead of two, blocks still of eight rows or
-        // more (level 0 of 513^3: 67.6 -> 57.8 us).  In FP32 the full span
-        // already holds three, and halving it measured slower (41.0 -> 47.6).
-        if constexpr (sizeof(T) == 8) {
-            constexpr int kHalf = rows_span<T>() / 2;
-            if (m.n * 8 <= kHalf) return launch_rows<T, kHalf>(F, m, tb, st);
-        }
         return launch_rows<T, rows_span<T>()>(F, m, tb, st);
     }
     if (m.inner > 1 && m.S <= kMaxSegWG) {
