@@ -957,8 +957,8 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     if (kt > 0) {
         MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
         if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
-        for (int i = 0; i < kt; i++) {
-            const int k = (i == 0) ? 0 : kt - i;  // finest first (own stream), then coarsest first
+        // one level step's correction on its own launches
+        auto single = [&](int k) -> int {
             hipStream_t sk = (k == 0) ? aux->s0 : aux->s;
             View3 cv = level_view(p, k);
             T* z = ws + p.Zrec[(size_t)k];
@@ -967,7 +967,68 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, k == 0);
             if (rc) return rc;
             MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
+            return MGR_OK;
+        };
+        // the coarser steps' corrections (coarsest first) share launches
+        // where their solves allow it: one load-vector launch and one launch
+        // per dimension for up to kMultiLevels steps, instead of a chain of
+        // small launches per step
+        std::vector<int> group;
+        auto flush = [&]() -> int {
+            const int n = (int)group.size();
+            if (n == 0) return MGR_OK;
+            if (n == 1) {
+                const int rc = single(group[0]);
+                group.clear();
+                return rc;
+            }
+            StreamArgs<T> la[kMultiLevels];
+            T* Fz[kMultiLevels];
+            View3 fv[kMultiLevels];
+            for (int i = 0; i < n; i++) {
+                const int k = group[(size_t)i];
+                const LevelLayout& ly = p.lv[(size_t)k];
+                StreamArgs<T>& a = la[i];
+                std::memset(&a, 0, sizeof(a));
+                a.A = src;
+                a.av = level_view(p, k);
+                a.cv = a.av;
+                a.wv = packed(ly.mc);
+                a.F = Fz[i] = ws + p.Zrec[(size_t)k];
+                a.fv = fv[i] = packed(ly.mc);
+                a.tb = tables_of<T>(p, k);
+            }
+            MGR_TRY(timed(KC_STREAM_LOAD, group[0], aux->s,
+                          [&] { return launch_stream_load_multi<T>(la, n, aux->s); }),
+                    "shared load-vector launch");
+            for (int sd = 0; sd < 3; sd++) {
+                const int d = 2 - sd;
+                if (!p.active[d]) continue;
+                SolveTables<T> tb[kMultiLevels];
+                for (int i = 0; i < n; i++) tb[i] = solve_tables_of<T>(p, group[(size_t)i], d);
+                MGR_TRY(timed(KC_SOLVE, group[0], aux->s,
+                              [&] { return launch_solve_multi<T>(Fz, fv, d, tb, n, aux->s); }),
+                        "shared solve launch");
+            }
+            for (int k : group) MGR_TRY(hipEventRecord(aux->done[k], aux->s), "level event");
+            group.clear();
+            return MGR_OK;
+        };
+        int rc = MGR_OK;
+        for (int k = kt - 1; k >= 1; k--) {
+            bool fits = true;
+            for (int d = 0; d < 3; d++)
+                if (p.active[d])
+                    fits = fits && solve_multi_fits<T>(packed(p.lv[(size_t)k].mc), d, solve_tables_of<T>(p, k, d));
+            if (fits) {
+                group.push_back(k);
+                if ((int)group.size() == kMultiLevels && (rc = flush())) return rc;
+            } else {
+                if ((rc = flush()) || (rc = single(k))) return rc;
+            }
         }
+        if ((rc = flush())) return rc;
+        if ((rc = single(0))) return rc;
     }
     for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];

@@ -136,6 +136,26 @@ hipError_t launch_tail_batch(const TailArgs<T>* dev_args, const int* field, cons
 
 template <typename T>
 hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st);
+
+// Independent level steps in one launch.  A recomposition's corrections
+// depend on the stored coefficients alone, so those of several level steps
+// can share one grid: its blocks are split between up to kMultiLevels steps,
+// each with the work split it would get alone and the same arithmetic.
+constexpr int kMultiLevels = 6;
+// Load vectors (no coefficients) of n level steps, all with the same active
+// dimensions.
+template <typename T>
+hipError_t launch_stream_load_multi(const StreamArgs<T>* a, int n, hipStream_t st);
+// Whether the solve along dimension d of a packed array of sizes fv takes a
+// single-launch form that launch_solve_multi can share.
+template <typename T>
+bool solve_multi_fits(View3 fv, int d, const SolveTables<T>& tb);
+// Solves along dimension d of n packed arrays F[i] (sizes fv[i], tables
+// tb[i]), in place, each fitting solve_multi_fits; the values are those of
+// launch_solve_partitioned.
+template <typename T>
+hipError_t launch_solve_multi(T* const* F, const View3* fv, int d, const SolveTables<T>* tb, int n,
+                              hipStream_t st);
 // One adjoint level step (mgr_adjoint.hip): g / gv the input at the level
 // grid's fine nodes, y the solved corrections and G the coarse-node input
 // (packed coarse grid yv), O / ov the level-grid output (not overlapping g).

@@ -25,6 +25,7 @@
 // fibre.  Longer fibres fall back to three launches (segment ends,
 // separators, final) through global memory.
 #include <algorithm>
+#include <cstring>
 
 #include "mgr_solve_dev.h"
 
@@ -183,7 +184,115 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
     for (int e = tid; e < V; e += kSmallThreads) a.F[e] = g[e];
 }
 
+// Solves of several level steps along one dimension in one grid: block b
+// belongs to the step l with start[l] <= b < start[l + 1].  Contiguous
+// dimension: each block solves rpb[l] rows staged through LDS (the rows
+// kernel's arithmetic); strided: 64 fibres, one wave per segment, waves past
+// a step's segment count idle through the barriers.
+template <typename T>
+struct MultiSolve {
+    T* F[kMultiLevels];
+    FibreMap m[kMultiLevels];
+    SolveTables<T> tb[kMultiLevels];
+    int rpb[kMultiLevels];
+    int start[kMultiLevels + 1];
+    int n;
+};
+static_assert(sizeof(MultiSolve<double>) <= 4096, "fits the kernel argument segment");
+
+template <typename T>
+__device__ __forceinline__ int multi_entry(const MultiSolve<T>& a, int b)
+{
+    int l = 0;
+    for (int i = 1; i < a.n; i++) l += (b >= a.start[i]) ? 1 : 0;
+    return l;
+}
+
+template <typename T, int kSpan>
+__global__ void __launch_bounds__(kBlk) k_solve_rows_multi(MultiSolve<T> a)
+{
+    __shared__ RowsSmem<T, kSpan, true> sm;
+    const int b = (int)blockIdx.x;
+    const int l = multi_entry(a, b);
+    const FibreMap& m = a.m[l];
+    const int64_t row0 = (int64_t)(b - a.start[l]) * a.rpb[l];
+    const int nrows = (int)min((int64_t)a.rpb[l], m.nfib - row0);
+    solve_rows_tile<T, kSpan, true>(a.F[l], m, a.tb[l], row0, nrows, sm);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kMaxSegWG) k_solve_strided_multi(MultiSolve<T> a)
+{
+    __shared__ StridedSmem<T> sm;
+    const int b = remap_xcd((int)blockIdx.x, (int)gridDim.x);
+    const int l = multi_entry(a, b);
+    const int s = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    solve_strided_tile<T, 64, false>(a.F[l], a.m[l], a.tb[l], (int64_t)(b - a.start[l]) * 64, s, (int)threadIdx.x,
+                                     (int)(64 * blockDim.y), (int)(threadIdx.y * 64 + threadIdx.x), sm);
+}
+
 }  // namespace
+
+template <typename T>
+bool solve_multi_fits(View3 fv, int d, const SolveTables<T>& tb)
+{
+    int64_t inner = 1;
+    for (int e = d + 1; e < 3; e++) inner *= fv.n[e];
+    if (tb.S < 1 || tb.S > kMaxSegWG) return false;
+    return inner > 1 || fv.n[d] <= rows_span<T>();
+}
+
+template <typename T>
+hipError_t launch_solve_multi(T* const* F, const View3* fv, int d, const SolveTables<T>* tb, int n, hipStream_t st)
+{
+    if (n < 1 || n > kMultiLevels) return hipErrorInvalidValue;
+    MultiSolve<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    bool rows = false;
+    int tot = 0, smax = 1;
+    for (int i = 0; i < n; i++) {
+        if (!solve_multi_fits<T>(fv[i], d, tb[i])) return hipErrorNotSupported;
+        FibreMap& m = a.m[i];
+        m.n = fv[i].n[d];
+        m.inner = 1;
+        m.outer = 1;
+        for (int e = d + 1; e < 3; e++) m.inner *= fv[i].n[e];
+        for (int e = 0; e < d; e++) m.outer *= fv[i].n[e];
+        m.nfib = m.inner * m.outer;
+        m.S = tb[i].S;
+        if (i == 0) rows = m.inner == 1;
+        if (rows != (m.inner == 1)) return hipErrorInvalidValue;
+        a.F[i] = F[i];
+        a.tb[i] = tb[i];
+        a.start[i] = tot;
+        if (rows) {
+            // the per-level rows launch's block size
+            const int64_t cus = 2 * (int64_t)device_cu_count();
+            const int64_t share = (m.nfib + cus - 1) / cus;
+            a.rpb[i] = (int)std::max<int64_t>(
+                1, std::min<int64_t>({(int64_t)(kBlk / m.S), (int64_t)(rows_span<T>() / m.n), share}));
+            tot += (int)((m.nfib + a.rpb[i] - 1) / a.rpb[i]);
+        } else {
+            a.rpb[i] = 64;
+            tot += (int)((m.nfib + 63) / 64);
+            smax = std::max(smax, m.S);
+        }
+    }
+    for (int i = n; i <= kMultiLevels; i++) a.start[i] = tot;
+    if (rows)
+        hipLaunchKernelGGL((k_solve_rows_multi<T, rows_span<T>()>), dim3((unsigned)tot), dim3(kBlk), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_solve_strided_multi<T>, dim3((unsigned)tot), dim3(64, (unsigned)smax), 0, st, a);
+    return hipGetLastError();
+}
+
+template bool solve_multi_fits<float>(View3, int, const SolveTables<float>&);
+template bool solve_multi_fits<double>(View3, int, const SolveTables<double>&);
+template hipError_t launch_solve_multi<float>(float* const*, const View3*, int, const SolveTables<float>*, int,
+                                              hipStream_t);
+template hipError_t launch_solve_multi<double>(double* const*, const View3*, int, const SolveTables<double>*, int,
+                                               hipStream_t);
 
 // Solve along dimension d of the packed array F (shape fv.n), in place.  Yb
 // is scratch of at least 2 * S * (number of fibres) elements.

@@ -25,6 +25,8 @@
 //               coarse values W and f.
 // kDec = false: input already holds coefficients at fine-only nodes (values
 //               at coarse positions are ignored); writes f only.
+#include <cstring>
+
 #include "mgr_stream_dev.h"
 
 namespace mgr {
@@ -38,28 +40,75 @@ k_stream_level(StreamArgs<T> a)
     stream_level_tile<T, kAct0, kAct1, kDec, kZ, kU>(a, remap_xcd((int)blockIdx.x, (int)gridDim.x), sm);
 }
 
+// Tiles and plane chunks of one level step (filled into a); returns its
+// workgroup count.
 template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
-hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st)
+int level_cfg(StreamArgs<T>& a)
 {
     using G = LevelGeom<kAct1, cols_per_lane<T>()>;
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
     a.nt1 = kAct1 ? (c1 + G::kT1 - 1) / G::kT1 : 1;
     a.nt2 = (c2 + G::kT2 - 1) / G::kT2;
     const int tiles = a.nt1 * a.nt2;
-    auto kern = k_stream_level<T, kAct0, kAct1, kDec, kZ, kU>;
     int chunk = c0;
     if (kAct0) {
         // One round of resident workgroups: a second, partial round would
         // run latency-bound on a mostly idle chip.
         static int occ = 0;
-        const int slots = resident_per_cu(kern, occ) * device_cu_count();
+        const int slots = resident_per_cu(k_stream_level<T, kAct0, kAct1, kDec, kZ, kU>, occ) * device_cu_count();
         const int nch = std::max(1, slots / tiles);
         chunk = (c0 + nch - 1) / nch;
         chunk = std::min(std::max(chunk, 2), kMaxChunk);
     }
     a.chunk = chunk;
     a.nch = kAct0 ? (c0 + chunk - 1) / chunk : 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * a.nch)), dim3(kThreads), 0, st, a);
+    return tiles * a.nch;
+}
+
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
+hipError_t launch_level_cfg(StreamArgs<T> a, hipStream_t st)
+{
+    const int blocks = level_cfg<T, kAct0, kAct1, kDec, kZ, kU>(a);
+    hipLaunchKernelGGL((k_stream_level<T, kAct0, kAct1, kDec, kZ, kU>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       st, a);
+    return hipGetLastError();
+}
+
+// Load-vector passes of several level steps in one grid: block b belongs to
+// the step l with start[l] <= b < start[l + 1] and is that step's workgroup
+// b - start[l].
+template <typename T>
+struct MultiStream {
+    StreamArgs<T> a[kMultiLevels];
+    int start[kMultiLevels + 1];
+    int n;
+};
+static_assert(sizeof(MultiStream<double>) <= 4096, "fits the kernel argument segment");
+
+template <typename T, bool kAct0, bool kAct1>
+__global__ void __launch_bounds__(kThreads) k_stream_load_multi(MultiStream<T> m)
+{
+    __shared__ LevelSmem<T, kAct0, kAct1, false> sm;
+    const int b = remap_xcd((int)blockIdx.x, (int)gridDim.x);
+    int l = 0;
+    for (int i = 1; i < m.n; i++) l += (b >= m.start[i]) ? 1 : 0;
+    stream_level_tile<T, kAct0, kAct1, false, false, false>(m.a[l], b - m.start[l], sm);
+}
+
+template <typename T, bool kAct0, bool kAct1>
+hipError_t launch_load_multi_cfg(const StreamArgs<T>* a, int n, hipStream_t st)
+{
+    MultiStream<T> m;
+    std::memset(&m, 0, sizeof(m));
+    m.n = n;
+    int tot = 0;
+    for (int i = 0; i < n; i++) {
+        m.a[i] = a[i];
+        m.start[i] = tot;
+        tot += level_cfg<T, kAct0, kAct1, false, false, false>(m.a[i]);
+    }
+    for (int i = n; i <= kMultiLevels; i++) m.start[i] = tot;
+    hipLaunchKernelGGL((k_stream_load_multi<T, kAct0, kAct1>), dim3((unsigned)tot), dim3(kThreads), 0, st, m);
     return hipGetLastError();
 }
 
@@ -107,7 +156,22 @@ hipError_t launch_stream_level(StreamArgs<T> a, bool dec, hipStream_t st)
     return hipErrorInvalidValue;  // (1, m1, m2) is never formed by the driver
 }
 
+template <typename T>
+hipError_t launch_stream_load_multi(const StreamArgs<T>* a, int n, hipStream_t st)
+{
+    if (n < 1 || n > kMultiLevels) return hipErrorInvalidValue;
+    const bool act0 = a[0].av.n[0] > 1, act1 = a[0].av.n[1] > 1;
+    for (int i = 1; i < n; i++)
+        if ((a[i].av.n[0] > 1) != act0 || (a[i].av.n[1] > 1) != act1) return hipErrorInvalidValue;
+    if (act0 && act1) return launch_load_multi_cfg<T, true, true>(a, n, st);
+    if (act0) return launch_load_multi_cfg<T, true, false>(a, n, st);
+    if (!act1) return launch_load_multi_cfg<T, false, false>(a, n, st);
+    return hipErrorInvalidValue;
+}
+
 template hipError_t launch_stream_level<float>(StreamArgs<float>, bool, hipStream_t);
 template hipError_t launch_stream_level<double>(StreamArgs<double>, bool, hipStream_t);
+template hipError_t launch_stream_load_multi<float>(const StreamArgs<float>*, int, hipStream_t);
+template hipError_t launch_stream_load_multi<double>(const StreamArgs<double>*, int, hipStream_t);
 
 }  // namespace mgr
