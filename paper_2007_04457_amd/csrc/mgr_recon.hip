@@ -59,11 +59,15 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon(StreamArgs<T> a)
     const int P0 = ch * a.chunk, P1 = min(P0 + a.chunk, c0);
     const int A1 = min(P1, c0 - 1);  // last coarse plane whose prolongation is needed
 
-    if (kAct0)
-        for (int e = tid; e < 2 * (2 * (A1 - P0) + 1); e += kThreads) {
-            const int f = 2 * P0 + e / 2;
-            sW0[e] = (f & 1) ? a.tb.w[0][2 * f + (e & 1)] : T(0);
-        }
+    // dim-0 weights of the chunk, staged once the first loads are issued
+    // (one memory latency then covers both)
+    auto stage_tables = [&] {
+        if (kAct0)
+            for (int e = tid; e < 2 * (2 * (A1 - P0) + 1); e += kThreads) {
+                const int f = 2 * P0 + e / 2;
+                sW0[e] = (f & 1) ? a.tb.w[0][2 * f + (e & 1)] : T(0);
+            }
+    };
 
     // ---- this lane's fine column and the wave's fine rows
     const int c = (wave % G::CW) * 64 + lane;
@@ -140,6 +144,7 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon(StreamArgs<T> a)
     load_tile(P0, pW, pZ);
     load_fine(2 * P0 - 1, false, fo);  // unused for the first plane (read but not emitted)
     load_fine(2 * P0, true, fe);
+    stage_tables();
 #pragma unroll
     for (int k = 0; k < NRW; k++) Qp[k] = T(0);
     lds_barrier();  // tables
@@ -237,17 +242,20 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon_al(StreamArgs<T> a)
     const int R0 = 2 * I1, C0 = 2 * I2;
     const bool first = t2 == 0, last = t2 == nt2 - 1;
 
-    if (kAct0)
-        for (int e = tid; e < 2 * (2 * (A1 - P0) + 1); e += kThreads) {
-            const int f = 2 * P0 + e / 2;
-            sW0[e] = (f & 1) ? a.tb.w[0][2 * f + (e & 1)] : T(0);
+    // dim-0 and column weights, staged once the first loads are issued
+    auto stage_tables = [&] {
+        if (kAct0)
+            for (int e = tid; e < 2 * (2 * (A1 - P0) + 1); e += kThreads) {
+                const int f = 2 * P0 + e / 2;
+                sW0[e] = (f & 1) ? a.tb.w[0][2 * f + (e & 1)] : T(0);
+            }
+        for (int e = tid; e < WC; e += kThreads) {
+            const int gc = C0 - WO + e;
+            const bool odd = (gc & 1) && gc > 0 && gc < m2;
+            sWc[2 * e] = odd ? a.tb.w[2][2 * gc] : T(1);
+            sWc[2 * e + 1] = odd ? a.tb.w[2][2 * gc + 1] : T(0);
         }
-    for (int e = tid; e < WC; e += kThreads) {
-        const int gc = C0 - WO + e;
-        const bool odd = (gc & 1) && gc > 0 && gc < m2;
-        sWc[2 * e] = odd ? a.tb.w[2][2 * gc] : T(1);
-        sWc[2 * e + 1] = odd ? a.tb.w[2][2 * gc + 1] : T(0);
-    }
+    };
     const int rg = wave;
     T wrl[NRW], wrh[NRW];
 #pragma unroll
@@ -340,6 +348,7 @@ __global__ void __launch_bounds__(kThreads) k_stream_recon_al(StreamArgs<T> a)
     load_tile(P0, pW, pZ);
     load_fine(2 * P0 - 1, fo);  // unused for the first plane (read but not emitted)
     load_fine(2 * P0, fe);
+    stage_tables();
     __syncthreads();  // tables
 
     for (int ac = P0; ac <= A1; ac++) {

@@ -143,19 +143,23 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
     const int tid = threadIdx.x;
     const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
     const int V = n0 * n1 * n2;
-    for (int e = tid; e < a.nd * 3 * kSlot; e += kSmallThreads) {
-        const int dd = e / (3 * kSlot), w = (e / kSlot) % 3, q = e % kSlot;
-        const T* src = (w == 0) ? a.L[dd] : (w == 1) ? a.U[dd] : a.IP[dd];
-        tab[e] = src[q];
-    }
-    // the grid in batches of 12 loads per lane, all in flight together
-    // (indices clamped into the grid: the loads are unconditional)
-    for (int b0 = 0; b0 < V; b0 += 12 * kSmallThreads) {
-        T tmp[12];
+    // the grid in batches of NB loads per lane, all in flight together
+    // (indices clamped into the grid: the loads are unconditional); one
+    // batch covers every grid that fits the LDS, and the tables are staged
+    // after its loads are issued, so one memory latency covers all
+    constexpr int NB = (sizeof(T) == 4) ? 40 : 20;
+    for (int b0 = 0; b0 < V; b0 += NB * kSmallThreads) {
+        T tmp[NB];
 #pragma unroll
-        for (int q = 0; q < 12; q++) tmp[q] = a.F[min(b0 + q * kSmallThreads + tid, V - 1)];
+        for (int q = 0; q < NB; q++) tmp[q] = a.F[min(b0 + q * kSmallThreads + tid, V - 1)];
+        if (b0 == 0)
+            for (int e = tid; e < a.nd * 3 * kSlot; e += kSmallThreads) {
+                const int dd = e / (3 * kSlot), w = (e / kSlot) % 3, q = e % kSlot;
+                const T* src = (w == 0) ? a.L[dd] : (w == 1) ? a.U[dd] : a.IP[dd];
+                tab[e] = src[q];
+            }
 #pragma unroll
-        for (int q = 0; q < 12; q++)
+        for (int q = 0; q < NB; q++)
             if (b0 + q * kSmallThreads + tid < V) g[b0 + q * kSmallThreads + tid] = tmp[q];
     }
     __syncthreads();

@@ -88,6 +88,21 @@ __device__ __forceinline__ void solve_strided_tile(T* __restrict__ F, const Fibr
                                                    int j, int nthr, int tid, StridedSmem<T>& sm)
 {
     const int S = m.S;
+    const bool inseg = kAllSeg || s < S;
+    const int sc = kAllSeg ? s : (inseg ? s : S - 1);
+    const int64_t fib = fib0 + j;
+    const bool active = inseg && fib < m.nfib;
+    const int64_t fc = fib < m.nfib ? fib : m.nfib - 1;  // idle lanes read a valid fibre
+    const int64_t base = (fc / m.inner) * m.n * m.inner + fc % m.inner;
+    int lo, len;
+    seg_range(m, sc, lo, len);
+    // the fibre loads are issued first and the tables' after them, so that
+    // one memory latency covers both (staging the tables first would wait
+    // for their loads before the fibre loads were issued)
+    T v[kSlot];
+#pragma unroll
+    for (int q = 0; q < kSlot; q++) v[q] = F[base + (int64_t)(lo + min(q, len - 1)) * m.inner];
+    const T fsep = F[base + (int64_t)(sc * kSeg) * m.inner];  // f at the segment's left separator
     for (int e = tid; e < S * kSlot; e += nthr) {
         sm.tab[0][e] = tb.L[e];
         sm.tab[1][e] = tb.U[e];
@@ -102,18 +117,7 @@ __device__ __forceinline__ void solve_strided_tile(T* __restrict__ F, const Fibr
         sm.septab[3][e] = tb.sip[e];
         sm.septab[4][e] = tb.su[e];
     }
-    const bool inseg = kAllSeg || s < S;
-    const int sc = kAllSeg ? s : (inseg ? s : S - 1);
-    const int64_t fib = fib0 + j;
-    const bool active = inseg && fib < m.nfib;
-    const int64_t fc = fib < m.nfib ? fib : m.nfib - 1;  // idle lanes read a valid fibre
-    const int64_t base = (fc / m.inner) * m.n * m.inner + fc % m.inner;
-    int lo, len;
-    seg_range(m, sc, lo, len);
-    T v[kSlot];
-#pragma unroll
-    for (int q = 0; q < kSlot; q++) v[q] = F[base + (int64_t)(lo + min(q, len - 1)) * m.inner];
-    if (inseg) sm.sep[s * FB + j] = (s > 0) ? F[base + (int64_t)(s * kSeg) * m.inner] : T(0);
+    if (inseg) sm.sep[s * FB + j] = (s > 0) ? fsep : T(0);
     __syncthreads();  // tables staged
     const T ylast = seg_solve(v, &sm.tab[0][sc * kSlot], &sm.tab[1][sc * kSlot], &sm.tab[2][sc * kSlot]);
     if (inseg) {
@@ -333,10 +337,11 @@ __device__ __forceinline__ void solve_rows_loop(T* __restrict__ F, const FibreMa
     auto span_of = [&](int64_t b) {
         return b < nblk ? (int)min((int64_t)rpb, m.nfib - b * rpb) * n : 0;
     };
-    rows_tables(m, tb, sm);
     T tmp[(kSpan + kBlk - 1) / kBlk];
     int64_t b = blockIdx.x;
     rows_load<T, kSpan>(F, b < nblk ? b * rpb : 0, span_of(b), n, tmp, (int)threadIdx.x);
+    // after the first block's loads were issued: one memory latency covers both
+    rows_tables(m, tb, sm);
     for (; b < nblk; b += gridDim.x) {
         const int span = span_of(b);
         rows_stage<T, kSpan, kLdsTab>(tmp, span, sm);

@@ -181,15 +181,19 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     const int F1 = kAct0 ? min(2 * P1, m0 - 1) : 0;
     const int oF0 = kAct0 ? 2 * P0 : 0, oF1 = kAct0 ? min(2 * P1, m0) : 1;
 
-    if (kDec && kAct0)
-        for (int e = tid; e < 2 * (F1 - F0 + 1); e += kThreads) sW0[e] = a.tb.w[0][2 * F0 + e];
-    if (kAct0)
-        // rows P0-1 .. P1+1, zero outside [P0, P1): no plane of another chunk
-        // receives contributions from this one
-        for (int e = tid; e < 5 * (P1 - P0 + 3); e += kThreads) {
-            const int i = P0 - 1 + e / 5;
-            sK0[e] = (i >= P0 && i < P1) ? a.tb.K[0][5 * i + e % 5] : T(0);
-        }
+    // dim-0 tables of the chunk, staged once the first planes' loads are
+    // issued (one memory latency then covers both)
+    auto stage_tables = [&] {
+        if (kDec && kAct0)
+            for (int e = tid; e < 2 * (F1 - F0 + 1); e += kThreads) sW0[e] = a.tb.w[0][2 * F0 + e];
+        if (kAct0)
+            // rows P0-1 .. P1+1, zero outside [P0, P1): no plane of another
+            // chunk receives contributions from this one
+            for (int e = tid; e < 5 * (P1 - P0 + 3); e += kThreads) {
+                const int i = P0 - 1 + e / 5;
+                sK0[e] = (i >= P0 && i < P1) ? a.tb.K[0][5 * i + e % 5] : T(0);
+            }
+    };
 
     // ---- this lane's staged columns cb .. cb + CPL - 1
     const int cb = ((wave % G::CW) * 64 + lane) * CPL;
@@ -476,11 +480,11 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
     for (int k = 0; k < NRW; k++)
 #pragma unroll
         for (int j = 0; j < CPL; j++) Pp[k][j] = Pn[k][j] = T(0);
-    lds_barrier();  // tables
     T g[NOUT];
 
     if (!kAct0) {
         load_plane(0, B0, Z0);
+        lds_barrier();  // (no dim-0 tables)
 #pragma unroll
         for (int k = 0; k < NRW; k++)
 #pragma unroll
@@ -504,6 +508,8 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
         load_plane(seq(2), B2, Z0);
         load_plane(seq(3), B3, Z0);
     }
+    stage_tables();
+    lds_barrier();  // tables
     // running dim-0 sums of coarse planes A = F0/2 + k, B = A + 1, Cc = A + 2
     T accA[NOUT], accB[NOUT], accC[NOUT];
 #pragma unroll
