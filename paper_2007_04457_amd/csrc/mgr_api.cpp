@@ -707,6 +707,21 @@ int solve_all(const Plan& p, int k, bool reverse, T* F, hipStream_t st, T* Yb = 
                     "small solve launch");
             return MGR_OK;
         }
+        // planes that fit in LDS: dimensions 2 and 1 in one launch, then 0
+        if (!reverse && p.active[1] && p.active[2]) {
+            const SolveTables<T> t2 = solve_tables_of<T>(p, k, 2), t1 = solve_tables_of<T>(p, k, 1);
+            if (solve_plane_fits<T>(fv, t2, t1)) {
+                MGR_TRY(timed(KC_SOLVE, k, st, [&] { return launch_solve_plane<T>(F, fv, t2, t1, st); }),
+                        "plane solve launch");
+                if (p.active[0]) {
+                    SolveTables<T> t0 = solve_tables_of<T>(p, k, 0);
+                    MGR_TRY(timed(KC_SOLVE, k, st,
+                                  [&] { return launch_solve_partitioned<T>(F, fv, 0, t0, Yb ? Yb : ws + p.Yb, st); }),
+                            "solve launch");
+                }
+                return MGR_OK;
+            }
+        }
     }
     for (int s = 0; s < 3; s++) {
         int d = reverse ? s : 2 - s;

@@ -95,6 +95,14 @@ template <typename T>
 hipError_t launch_solve_small(T* F, View3 fv, const int* dims, int nd, const SolveTables<T>* tb, hipStream_t st);
 template <typename T>
 bool solve_small_fits(View3 fv, const int* dims, int nd, const SolveTables<T>* tb);
+// Dimensions 2 and then 1 of the packed array F (sizes fv, 3-D) in one
+// launch, a workgroup per plane along dim 0, when its planes fit in LDS
+// (solve_plane_fits); the values are those of launch_solve_partitioned along
+// dimension 2 and then 1.
+template <typename T>
+bool solve_plane_fits(View3 fv, const SolveTables<T>& t2, const SolveTables<T>& t1);
+template <typename T>
+hipError_t launch_solve_plane(T* F, View3 fv, const SolveTables<T>& t2, const SolveTables<T>& t1, hipStream_t st);
 
 // Single-workgroup kernel for the small coarse levels (mgr_tail.hip): all
 // level steps k0 .. k0 + nlev - 1 in one launch, in LDS.  A level step may

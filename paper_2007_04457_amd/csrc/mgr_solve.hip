@@ -188,6 +188,115 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
     for (int e = tid; e < V; e += kSmallThreads) a.F[e] = g[e];
 }
 
+constexpr int kPlaneThreads = 1024;  // largest plane-solve workgroup
+
+// Dimensions 2 and then 1 of a coarse grid whose planes (a fixed index along
+// dim 0) fit in LDS: one workgroup per plane stages it, solves every row and
+// then every column in LDS with the partitioned arithmetic of the
+// per-dimension kernels (seg_solve, the separator system, seg_final: the same
+// values), and writes it back, in one launch and one pass over the array
+// instead of two.  One thread per (segment, fibre) task, fibres fastest, so
+// that lanes read LDS at the fibres' stride (odd for 2^k + 1 sizes: no bank
+// conflicts) or contiguously.
+template <typename T>
+struct PlaneSolveArgs {
+    T* F;
+    int n1, n2;
+    SolveTables<T> tb[2];  // dimension 2, dimension 1
+};
+
+template <typename T>
+__device__ __forceinline__ void plane_dim(T* P, T* end0, T* end1, const T* tab, const T* septab, int n, int S,
+                                          int nf, int sd, int sf, int tid)
+{
+    // task tid: segment s of fibre f; fibre f starts at P[f sf], node i of it
+    // is at P[f sf + i sd]
+    const bool active = tid < S * nf;
+    const int s = active ? tid / nf : 0, f = active ? tid % nf : 0;
+    FibreMap m;
+    m.n = n;
+    m.S = S;
+    int lo, len;
+    seg_range(m, s, lo, len);
+    T* const p = P + f * sf;
+    T v[kSlot];
+#pragma unroll
+    for (int q = 0; q < kSlot; q++) v[q] = p[(lo + min(q, len - 1)) * sd];
+    const T ylast = seg_solve(v, tab + 0 * kMaxSegWG * kSlot + s * kSlot, tab + 1 * kMaxSegWG * kSlot + s * kSlot,
+                              tab + 2 * kMaxSegWG * kSlot + s * kSlot);
+    if (active) {
+        end0[s * nf + f] = v[0];
+        end1[s * nf + f] = ylast;
+    }
+    __syncthreads();
+    if (active && s == 0 && S > 1)
+        sep_solve(S, p, (int64_t)kSeg * sd, end0 + f, end1 + f, nf, septab + 0 * kMaxSegWG,
+                  septab + 1 * kMaxSegWG, septab + 2 * kMaxSegWG, septab + 3 * kMaxSegWG, septab + 4 * kMaxSegWG);
+    __syncthreads();
+    const T zl = (s > 0) ? p[(s * kSeg) * sd] : T(0);
+    const T zr = (s < S - 1) ? p[((s + 1) * kSeg) * sd] : T(0);
+    __syncthreads();  // every task has read its separators
+    if (active) {
+        const T* ta = tab + 3 * kMaxSegWG * kSlot + s * kSlot;
+        const T* tb = tab + 4 * kMaxSegWG * kSlot + s * kSlot;
+#pragma unroll
+        for (int q = 0; q < kSlot; q++)
+            if (q < len) p[(lo + q) * sd] = seg_final(v[q], ta[q], zl, tb[q], zr);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPlaneThreads) k_solve_plane(PlaneSolveArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char plane_lds[];
+    constexpr int TAB = 5 * kMaxSegWG * kSlot, SEP = 5 * kMaxSegWG;
+    T* const tab = reinterpret_cast<T*>(plane_lds);  // [dim][L, U, IP, A, B][segment][slot]
+    T* const septab = tab + 2 * TAB;                  // [dim][sub, sup, sl, sip, su][separator]
+    T* const end = septab + 2 * SEP;                  // [2][kPlaneThreads]
+    T* const P = end + 2 * kPlaneThreads;             // the plane, n1 x n2
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int n1 = a.n1, n2 = a.n2, V = n1 * n2;
+    T* const F = a.F + (int64_t)blockIdx.x * V;
+    // the plane's loads first (one batch covers every plane that fits), the
+    // tables' after them: one memory latency covers both
+    constexpr int NB = (sizeof(T) == 4) ? 20 : 10;
+    for (int b0 = 0; b0 < V; b0 += NB * nthr) {
+        T tmp[NB];
+#pragma unroll
+        for (int q = 0; q < NB; q++) tmp[q] = F[min(b0 + q * nthr + tid, V - 1)];
+        if (b0 == 0)
+            for (int d = 0; d < 2; d++) {
+                const SolveTables<T>& t = a.tb[d];
+                for (int e = tid; e < t.S * kSlot; e += nthr) {
+                    T* o = tab + d * TAB + e;
+                    o[0 * kMaxSegWG * kSlot] = t.L[e];
+                    o[1 * kMaxSegWG * kSlot] = t.U[e];
+                    o[2 * kMaxSegWG * kSlot] = t.IP[e];
+                    o[3 * kMaxSegWG * kSlot] = t.A[e];
+                    o[4 * kMaxSegWG * kSlot] = t.B[e];
+                }
+                for (int e = tid; e < t.S; e += nthr) {
+                    T* o = septab + d * SEP + e;
+                    o[0 * kMaxSegWG] = t.ssub[e];
+                    o[1 * kMaxSegWG] = t.ssup[e];
+                    o[2 * kMaxSegWG] = t.sl[e];
+                    o[3 * kMaxSegWG] = t.sip[e];
+                    o[4 * kMaxSegWG] = t.su[e];
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < NB; q++)
+            if (b0 + q * nthr + tid < V) P[b0 + q * nthr + tid] = tmp[q];
+    }
+    __syncthreads();
+    // rows (dimension 2): fibre f = row, node i at f n2 + i
+    plane_dim(P, end, end + kPlaneThreads, tab, septab, n2, a.tb[0].S, n1, 1, n2, tid);
+    // columns (dimension 1): fibre f = column, node i at i n2 + f
+    plane_dim(P, end, end + kPlaneThreads, tab + TAB, septab + SEP, n1, a.tb[1].S, n2, n2, 1, tid);
+    for (int e = tid; e < V; e += nthr) F[e] = P[e];
+}
+
 // Solves of several level steps along one dimension in one grid: block b
 // belongs to the step l with start[l] <= b < start[l + 1].  Contiguous
 // dimension: each block solves rpb[l] rows staged through LDS (the rows
@@ -388,6 +497,66 @@ hipError_t launch_solve_small(T* F, View3 fv, const int* dims, int nd, const Sol
     hipLaunchKernelGGL(k_solve_small<T>, dim3(1), dim3(kSmallThreads), small_solve_bytes<T>(fv), st, a);
     return hipGetLastError();
 }
+
+// LDS the plane-solve kernel may use on the current device (0: none).
+template <typename T>
+int plane_solve_lds()
+{
+    static int max_lds[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (max_lds[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        max_lds[dev] = v;
+        if (v > 65536 &&
+            hipFuncSetAttribute((const void*)k_solve_plane<T>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+                hipSuccess) {
+            (void)hipGetLastError();  // not sticky: keep it from the next launch check
+            max_lds[dev] = 65536;
+        }
+    }
+    return max_lds[dev];
+}
+
+template <typename T>
+size_t plane_solve_bytes(View3 fv)
+{
+    return (size_t)(10 * kMaxSegWG * kSlot + 10 * kMaxSegWG + 2 * kPlaneThreads + fv.n[1] * fv.n[2]) * sizeof(T);
+}
+
+template <typename T>
+bool solve_plane_fits(View3 fv, const SolveTables<T>& t2, const SolveTables<T>& t1)
+{
+    if (fv.n[1] < 2 || fv.n[2] < 2 || t2.S < 1 || t1.S < 1 || t2.S > kMaxSegWG || t1.S > kMaxSegWG) return false;
+    if (t2.S * fv.n[1] > kPlaneThreads || t1.S * fv.n[2] > kPlaneThreads) return false;
+    if (fv.n[1] > kSlot * kMaxSegWG || fv.n[2] > kSlot * kMaxSegWG) return false;
+    return plane_solve_bytes<T>(fv) <= (size_t)plane_solve_lds<T>();
+}
+
+template <typename T>
+hipError_t launch_solve_plane(T* F, View3 fv, const SolveTables<T>& t2, const SolveTables<T>& t1, hipStream_t st)
+{
+    if (!solve_plane_fits<T>(fv, t2, t1)) return hipErrorNotSupported;
+    PlaneSolveArgs<T> a;
+    a.F = F;
+    a.n1 = (int)fv.n[1];
+    a.n2 = (int)fv.n[2];
+    a.tb[0] = t2;
+    a.tb[1] = t1;
+    const int64_t tasks = std::max<int64_t>(t2.S * fv.n[1], t1.S * fv.n[2]);
+    const unsigned thr = (unsigned)std::min<int64_t>(kPlaneThreads, std::max<int64_t>(64, (tasks + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_solve_plane<T>, dim3((unsigned)fv.n[0]), dim3(thr), plane_solve_bytes<T>(fv), st, a);
+    return hipGetLastError();
+}
+
+template bool solve_plane_fits<float>(View3, const SolveTables<float>&, const SolveTables<float>&);
+template bool solve_plane_fits<double>(View3, const SolveTables<double>&, const SolveTables<double>&);
+template hipError_t launch_solve_plane<float>(float*, View3, const SolveTables<float>&, const SolveTables<float>&,
+                                              hipStream_t);
+template hipError_t launch_solve_plane<double>(double*, View3, const SolveTables<double>&,
+                                               const SolveTables<double>&, hipStream_t);
 
 template bool solve_small_fits<float>(View3, const int*, int, const SolveTables<float>*);
 template bool solve_small_fits<double>(View3, const int*, int, const SolveTables<double>*);

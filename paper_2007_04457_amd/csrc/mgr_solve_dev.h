@@ -48,6 +48,32 @@ __device__ __forceinline__ T seg_solve(T (&v)[kSlot], const T* L, const T* U, co
     return last;
 }
 
+// Separator elimination and the segments' final values with one fixed
+// rounding (explicit FMAs), shared by every solve form so that they all give
+// the same values: right-hand side of separator k from f there and the
+// neighbouring segments' end values, its forward elimination, its back
+// substitution, and z = y + alpha z_left + beta z_right in a segment.
+template <typename T>
+__device__ __forceinline__ T sep_rhs(T f, T sub, T ylast, T sup, T yfirst)
+{
+    return fma(-sup, yfirst, fma(-sub, ylast, f));
+}
+template <typename T>
+__device__ __forceinline__ T sep_fwd(T rhs, T l, T g)
+{
+    return fma(-l, g, rhs);
+}
+template <typename T>
+__device__ __forceinline__ T sep_bwd(T f, T u, T z, T ip)
+{
+    return fma(-u, z, f) * ip;
+}
+template <typename T>
+__device__ __forceinline__ T seg_final(T y, T alpha, T zl, T beta, T zr)
+{
+    return fma(beta, zr, fma(alpha, zl, y));
+}
+
 // Separator system of one fibre from the separator f values (in sep[], which
 // receives z) and the segment-end values; coefficient tables per separator.
 template <typename T>
@@ -58,13 +84,13 @@ __device__ __forceinline__ void sep_solve(int S, T* sep, int64_t sstride, const 
 {
     T g = T(0);
     for (int k = 1; k < S; k++) {
-        const T rhs = sep[k * sstride] - ssub[k] * ylast[(k - 1) * ystride] - ssup[k] * yfirst[k * ystride];
-        g = (k == 1) ? rhs : rhs - sl[k] * g;
+        const T rhs = sep_rhs(sep[k * sstride], ssub[k], ylast[(k - 1) * ystride], ssup[k], yfirst[k * ystride]);
+        g = (k == 1) ? rhs : sep_fwd(rhs, sl[k], g);
         sep[k * sstride] = g;
     }
     T z = T(0);
     for (int k = S - 1; k >= 1; k--) {
-        z = (k == S - 1) ? sep[k * sstride] * sip[k] : (sep[k * sstride] - su[k] * z) * sip[k];
+        z = (k == S - 1) ? sep[k * sstride] * sip[k] : sep_bwd(sep[k * sstride], su[k], z, sip[k]);
         sep[k * sstride] = z;
     }
 }
@@ -136,7 +162,7 @@ __device__ __forceinline__ void solve_strided_tile(T* __restrict__ F, const Fibr
     const T* tbt = &sm.tab[4][s * kSlot];
 #pragma unroll
     for (int q = 0; q < kSlot; q++)
-        if (q < len) F[base + (int64_t)(lo + q) * m.inner] = v[q] + ta[q] * zl + tbt[q] * zr;
+        if (q < len) F[base + (int64_t)(lo + q) * m.inner] = seg_final(v[q], ta[q], zl, tbt[q], zr);
     if (s > 0) F[base + (int64_t)(s * kSeg) * m.inner] = zl;
 }
 
@@ -248,14 +274,14 @@ __device__ __forceinline__ void rows_solve_lds(const FibreMap& m, const SolveTab
         T gg = T(0);
         for (int k = 1; k < m.S; k++) {
             const int e = padded(r * n + k * kSeg);
-            const T rhs = sm.f[e] - sm.septab[0][k] * sm.end[1][t0 + k - 1] - sm.septab[1][k] * sm.end[0][t0 + k];
-            gg = (k == 1) ? rhs : rhs - sm.septab[2][k] * gg;
+            const T rhs = sep_rhs(sm.f[e], sm.septab[0][k], sm.end[1][t0 + k - 1], sm.septab[1][k], sm.end[0][t0 + k]);
+            gg = (k == 1) ? rhs : sep_fwd(rhs, sm.septab[2][k], gg);
             sm.f[e] = gg;
         }
         T z = T(0);
         for (int k = m.S - 1; k >= 1; k--) {
             const int e = padded(r * n + k * kSeg);
-            z = (k == m.S - 1) ? sm.f[e] * sm.septab[3][k] : (sm.f[e] - sm.septab[4][k] * z) * sm.septab[3][k];
+            z = (k == m.S - 1) ? sm.f[e] * sm.septab[3][k] : sep_bwd(sm.f[e], sm.septab[4][k], z, sm.septab[3][k]);
             sm.f[e] = z;
         }
     }
@@ -266,7 +292,7 @@ __device__ __forceinline__ void rows_solve_lds(const FibreMap& m, const SolveTab
     if (active) {
 #pragma unroll
         for (int q = 0; q < kSlot; q++)
-            if (q < len) sm.f[padded(r * n + lo + q)] = v[q] + tA[q] * zl + tB[q] * zr;
+            if (q < len) sm.f[padded(r * n + lo + q)] = seg_final(v[q], tA[q], zl, tB[q], zr);
     }
     bar();
 }
@@ -437,7 +463,8 @@ __device__ __forceinline__ void seg_final_tile(T* __restrict__ F, const FibreMap
     const T zr = (s < m.S - 1) ? F[base + (int64_t)((s + 1) * kSeg) * m.inner] : T(0);
 #pragma unroll
     for (int q = 0; q < kSlot; q++)
-        if (q < len) F[base + (int64_t)(lo + q) * m.inner] = v[q] + tb.A[s * kSlot + q] * zl + tb.B[s * kSlot + q] * zr;
+        if (q < len)
+            F[base + (int64_t)(lo + q) * m.inner] = seg_final(v[q], tb.A[s * kSlot + q], zl, tb.B[s * kSlot + q], zr);
 }
 
 }  // namespace
