@@ -45,7 +45,7 @@ k_stream_level(StreamArgs<T> a)
 template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
 int level_cfg(StreamArgs<T>& a)
 {
-    using G = LevelGeom<kAct1, cols_per_lane<T>()>;
+    using G = LevelGeom<kAct1, cols_per_lane<T>(), wide_tile<T>()>;
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
     a.nt1 = kAct1 ? (c1 + G::kT1 - 1) / G::kT1 : 1;
     a.nt2 = (c2 + G::kT2 - 1) / G::kT2;
@@ -138,11 +138,11 @@ void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2)
 {
     constexpr int Cf = cols_per_lane<float>(), Cd = cols_per_lane<double>();
     if (elem_bytes == 4) {
-        *kT1 = act1 ? LevelGeom<true, Cf>::kT1 : LevelGeom<false, Cf>::kT1;
-        *kT2 = act1 ? LevelGeom<true, Cf>::kT2 : LevelGeom<false, Cf>::kT2;
+        *kT1 = act1 ? LevelGeom<true, Cf, wide_tile<float>()>::kT1 : LevelGeom<false, Cf, false>::kT1;
+        *kT2 = act1 ? LevelGeom<true, Cf, wide_tile<float>()>::kT2 : LevelGeom<false, Cf, false>::kT2;
     } else {
-        *kT1 = act1 ? LevelGeom<true, Cd>::kT1 : LevelGeom<false, Cd>::kT1;
-        *kT2 = act1 ? LevelGeom<true, Cd>::kT2 : LevelGeom<false, Cd>::kT2;
+        *kT1 = act1 ? LevelGeom<true, Cd, wide_tile<double>()>::kT1 : LevelGeom<false, Cd, false>::kT1;
+        *kT2 = act1 ? LevelGeom<true, Cd, wide_tile<double>()>::kT2 : LevelGeom<false, Cd, false>::kT2;
     }
 }
 
