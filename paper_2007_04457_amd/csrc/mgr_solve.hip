@@ -188,7 +188,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_solve_small(SmallSolveArgs<T>
     for (int e = tid; e < V; e += kSmallThreads) a.F[e] = g[e];
 }
 
-constexpr int kPlaneThreads = 1024;  // largest plane-solve workgroup
+// Largest plane-solve workgroup: ten waves, so that the compiler may give a
+// lane up to 168 registers (the FP64 kernel spilled at the 128 of 16 waves).
+constexpr int kPlaneThreads = 640;
 
 // Dimensions 2 and then 1 of a coarse grid whose planes (a fixed index along
 // dim 0) fit in LDS: one workgroup per plane stages it, solves every row and
@@ -333,8 +335,10 @@ __global__ void __launch_bounds__(kBlk) k_solve_rows_multi(MultiSolve<T> a)
     solve_rows_tile<T, kSpan, true>(a.F[l], m, a.tb[l], row0, nrows, sm);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64 * kMaxSegWG) k_solve_strided_multi(MultiSolve<T> a)
+// kMaxThr: the launch's bound (512 when every step has at most 8 segments,
+// which leaves the compiler twice the registers of the 1024-thread form).
+template <typename T, int kMaxThr>
+__global__ void __launch_bounds__(kMaxThr) k_solve_strided_multi(MultiSolve<T> a)
 {
     __shared__ StridedSmem<T> sm;
     const int b = remap_xcd((int)blockIdx.x, (int)gridDim.x);
@@ -395,8 +399,11 @@ hipError_t launch_solve_multi(T* const* F, const View3* fv, int d, const SolveTa
     for (int i = n; i <= kMultiLevels; i++) a.start[i] = tot;
     if (rows)
         hipLaunchKernelGGL((k_solve_rows_multi<T, rows_span<T>()>), dim3((unsigned)tot), dim3(kBlk), 0, st, a);
+    else if (smax <= 8)
+        hipLaunchKernelGGL((k_solve_strided_multi<T, 512>), dim3((unsigned)tot), dim3(64, (unsigned)smax), 0, st, a);
     else
-        hipLaunchKernelGGL(k_solve_strided_multi<T>, dim3((unsigned)tot), dim3(64, (unsigned)smax), 0, st, a);
+        hipLaunchKernelGGL((k_solve_strided_multi<T, 64 * kMaxSegWG>), dim3((unsigned)tot), dim3(64, (unsigned)smax), 0,
+                           st, a);
     return hipGetLastError();
 }
 
