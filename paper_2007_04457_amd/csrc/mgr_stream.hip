@@ -45,7 +45,7 @@ k_stream_level(StreamArgs<T> a)
 template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
 int level_cfg(StreamArgs<T>& a)
 {
-    using G = LevelGeom<kAct1, cols_per_lane<T>(), wide_tile<T>()>;
+    using G = LevelGeom<kAct1, cols_per_lane<T>(), wide_tile<T, kDec>()>;
     const int c0 = (int)a.fv.n[0], c1 = (int)a.fv.n[1], c2 = (int)a.fv.n[2];
     a.nt1 = kAct1 ? (c1 + G::kT1 - 1) / G::kT1 : 1;
     a.nt2 = (c2 + G::kT2 - 1) / G::kT2;
@@ -133,16 +133,16 @@ hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
 
 }  // namespace
 
-// Coarse rows and columns of a streaming tile (for the batch's work items).
+// Coarse rows and columns of a decomposition tile (for the batch's work items).
 void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2)
 {
     constexpr int Cf = cols_per_lane<float>(), Cd = cols_per_lane<double>();
     if (elem_bytes == 4) {
-        *kT1 = act1 ? LevelGeom<true, Cf, wide_tile<float>()>::kT1 : LevelGeom<false, Cf, false>::kT1;
-        *kT2 = act1 ? LevelGeom<true, Cf, wide_tile<float>()>::kT2 : LevelGeom<false, Cf, false>::kT2;
+        *kT1 = act1 ? LevelGeom<true, Cf, wide_tile<float, true>()>::kT1 : LevelGeom<false, Cf, false>::kT1;
+        *kT2 = act1 ? LevelGeom<true, Cf, wide_tile<float, true>()>::kT2 : LevelGeom<false, Cf, false>::kT2;
     } else {
-        *kT1 = act1 ? LevelGeom<true, Cd, wide_tile<double>()>::kT1 : LevelGeom<false, Cd, false>::kT1;
-        *kT2 = act1 ? LevelGeom<true, Cd, wide_tile<double>()>::kT2 : LevelGeom<false, Cd, false>::kT2;
+        *kT1 = act1 ? LevelGeom<true, Cd, wide_tile<double, true>()>::kT1 : LevelGeom<false, Cd, false>::kT1;
+        *kT2 = act1 ? LevelGeom<true, Cd, wide_tile<double, true>()>::kT2 : LevelGeom<false, Cd, false>::kT2;
     }
 }
 

@@ -72,13 +72,15 @@ constexpr int cols_per_lane()
 {
     return 1;
 }
-// Wide 3-D tiles for FP64 (measured: level 0 of 513^3 0.75 -> 0.68 ms); FP32
-// keeps narrow tiles, whose fewer rows per wave leave room for the deeper
-// register ring (wide tiles with the two-plane ring measured slower there).
-template <typename T>
+// Wide 3-D tiles for FP64 (measured: level 0 of 513^3 0.75 -> 0.68 ms) and
+// for the FP32 load-vector pass (kDec false, which runs the two-plane ring
+// anyway); the FP32 decomposition pass keeps narrow tiles, whose fewer rows
+// per wave leave room for its deeper register ring (wide tiles with the
+// two-plane ring measured slower there).
+template <typename T, bool kDec>
 constexpr bool wide_tile()
 {
-    return sizeof(T) == 8;
+    return sizeof(T) == 8 || !kDec;
 }
 
 constexpr int kMaxChunk = 128;       // coarse planes per workgroup (LDS tables)
@@ -146,7 +148,7 @@ __device__ __forceinline__ void buf_store_cols(const T (&v)[N], __amdgpu_buffer_
 // the chunk.
 template <typename T, bool kAct0, bool kAct1, bool kDec>
 struct alignas(16) LevelSmem {
-    using G = LevelGeom<kAct1, cols_per_lane<T>(), wide_tile<T>()>;
+    using G = LevelGeom<kAct1, cols_per_lane<T>(), wide_tile<T, kDec>()>;
     T sU[kDec ? G::NR * G::NCW : 1];
     T sC[G::OB + G::NR * G::H];
     T sG[G::NR * G::GW];
@@ -164,7 +166,7 @@ __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bi
                                                   LevelSmem<T, kAct0, kAct1, kDec>& sm)
 {
     constexpr int CPL = cols_per_lane<T>();
-    using G = LevelGeom<kAct1, CPL, wide_tile<T>()>;
+    using G = LevelGeom<kAct1, CPL, wide_tile<T, kDec>()>;
     constexpr int NR = G::NR, NCW = G::NCW, NRW = G::NRW, RW = G::RW, H = G::H, GW = G::GW;
     constexpr int kT1 = G::kT1, kT2 = G::kT2, OB = G::OB;
     constexpr int NGP = (NR + (kThreads / GW) - 1) / (kThreads / GW);  // dim-2 passes
