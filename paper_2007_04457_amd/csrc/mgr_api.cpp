@@ -969,6 +969,7 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
                       [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), sc); }),
                 "coarsest gather");
     }
+    int cdone[kMaxLevels] = {};  // per level step: the event (done[i]) recorded once its correction is done
     if (kt > 0) {
         MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
         if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
@@ -982,6 +983,7 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, k == 0);
             if (rc) return rc;
             MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
+            cdone[k] = k;
             return MGR_OK;
         };
         // the coarser steps' corrections (coarsest first) share launches
@@ -1025,7 +1027,10 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
                               [&] { return launch_solve_multi<T>(Fz, fv, d, tb, n, aux->s); }),
                         "shared solve launch");
             }
-            for (int k : group) MGR_TRY(hipEventRecord(aux->done[k], aux->s), "level event");
+            // one event marks the whole group's corrections done
+            const int last = group.back();
+            MGR_TRY(hipEventRecord(aux->done[last], aux->s), "level event");
+            for (int k : group) cdone[k] = last;
             group.clear();
             return MGR_OK;
         };
@@ -1045,6 +1050,7 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
         if ((rc = flush())) return rc;
         if ((rc = single(0))) return rc;
     }
+    int waited = -1;  // the correction event the interpolation stream last waited for
     for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
         View3 cv = level_view(p, k);
@@ -1053,8 +1059,13 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             // join: the coarser interpolations (sr) and the finest correction
             MGR_TRY(hipEventRecord(aux->rdone, sc), "join event");
             MGR_TRY(hipStreamWaitEvent(st, aux->rdone, 0), "join wait");
+            MGR_TRY(hipStreamWaitEvent(st, aux->done[0], 0), "level wait");
+        } else if (cdone[k] != waited) {
+            // each wait costs the interpolation chain a few microseconds even
+            // when the event has completed: one per group of corrections
+            MGR_TRY(hipStreamWaitEvent(sk, aux->done[cdone[k]], 0), "level wait");
+            waited = cdone[k];
         }
-        MGR_TRY(hipStreamWaitEvent(sk, aux->done[k], 0), "level wait");
         StreamArgs<T> a;
         a.A = src;
         a.Z = ws + p.Zrec[(size_t)k];
