@@ -950,13 +950,22 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     const int kt = tail_start(p);
     std::unique_lock<std::mutex> lk(g_aux_mu);
     AuxStream* aux = nullptr;
-    hipStream_t sc = st;  // the stream of the tail and the coarser interpolations
+    // Streams: the caller's (the coarser corrections and interpolations,
+    // then the finest interpolation), sr (the tail) and s0 (the finest
+    // correction), both forked from the caller's.  The coarser chain is the
+    // longest, so it stays on the caller's stream: no fork delays its start,
+    // and it waits on other streams only twice (the tail before its first
+    // interpolation, the finest correction before the last); a wait on
+    // another stream's event costs the waiting stream several microseconds
+    // even when the event has long completed.
+    hipStream_t sc = st;  // the stream of the tail
     if (kt > 0) {
         if (!aux_ready() && capturing(st))
             return fail(MGR_ERR_CAPTURE, "auxiliary streams not created and the stream is capturing; call mgr_prepare first");
         MGR_TRY(aux_stream(&aux), "auxiliary stream");
         MGR_TRY(hipEventRecord(aux->start, st), "fork event");
         MGR_TRY(hipStreamWaitEvent(aux->sr, aux->start, 0), "fork wait");
+        MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
         sc = aux->sr;
     }
     if (kt < L) {
@@ -969,23 +978,24 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
                       [&] { return launch_copy_view<T>(src, nullptr, cl, ws + p.Woff[(size_t)L], packed(cl.n), sc); }),
                 "coarsest gather");
     }
-    int cdone[kMaxLevels] = {};  // per level step: the event (done[i]) recorded once its correction is done
     if (kt > 0) {
-        MGR_TRY(hipStreamWaitEvent(aux->s0, aux->start, 0), "fork wait");
-        if (kt > 1) MGR_TRY(hipStreamWaitEvent(aux->s, aux->start, 0), "fork wait");
-        // one level step's correction on its own launches
+        MGR_TRY(hipEventRecord(aux->rdone, sc), "tail event");
+        // one level step's correction on its own launches (the finest on s0)
         auto single = [&](int k) -> int {
-            hipStream_t sk = (k == 0) ? aux->s0 : aux->s;
+            hipStream_t sk = (k == 0) ? aux->s0 : st;
             View3 cv = level_view(p, k);
             T* z = ws + p.Zrec[(size_t)k];
             int rc = stream_level<T>(p, k, false, src, nullptr, cv, nullptr, cv, nullptr, false, sk, z);
             if (rc) return rc;
             rc = solve_all<T>(p, k, false, z, sk, (k == 0) ? ws + p.Yb : ws + p.Yb2, k == 0);
             if (rc) return rc;
-            MGR_TRY(hipEventRecord(aux->done[k], sk), "level event");
-            cdone[k] = k;
+            if (k == 0) MGR_TRY(hipEventRecord(aux->done[0], sk), "level event");
             return MGR_OK;
         };
+        // the finest step's correction first, so that its launches reach the
+        // device together with the coarser chain's
+        int rc = single(0);
+        if (rc) return rc;
         // the coarser steps' corrections (coarsest first) share launches
         // where their solves allow it: one load-vector launch and one launch
         // per dimension for up to kMultiLevels steps, instead of a chain of
@@ -995,9 +1005,9 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             const int n = (int)group.size();
             if (n == 0) return MGR_OK;
             if (n == 1) {
-                const int rc = single(group[0]);
+                const int rc1 = single(group[0]);
                 group.clear();
-                return rc;
+                return rc1;
             }
             StreamArgs<T> la[kMultiLevels];
             T* Fz[kMultiLevels];
@@ -1015,26 +1025,19 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
                 a.fv = fv[i] = packed(ly.mc);
                 a.tb = tables_of<T>(p, k);
             }
-            MGR_TRY(timed(KC_STREAM_LOAD, group[0], aux->s,
-                          [&] { return launch_stream_load_multi<T>(la, n, aux->s); }),
+            MGR_TRY(timed(KC_STREAM_LOAD, group[0], st, [&] { return launch_stream_load_multi<T>(la, n, st); }),
                     "shared load-vector launch");
             for (int sd = 0; sd < 3; sd++) {
                 const int d = 2 - sd;
                 if (!p.active[d]) continue;
                 SolveTables<T> tb[kMultiLevels];
                 for (int i = 0; i < n; i++) tb[i] = solve_tables_of<T>(p, group[(size_t)i], d);
-                MGR_TRY(timed(KC_SOLVE, group[0], aux->s,
-                              [&] { return launch_solve_multi<T>(Fz, fv, d, tb, n, aux->s); }),
+                MGR_TRY(timed(KC_SOLVE, group[0], st, [&] { return launch_solve_multi<T>(Fz, fv, d, tb, n, st); }),
                         "shared solve launch");
             }
-            // one event marks the whole group's corrections done
-            const int last = group.back();
-            MGR_TRY(hipEventRecord(aux->done[last], aux->s), "level event");
-            for (int k : group) cdone[k] = last;
             group.clear();
             return MGR_OK;
         };
-        int rc = MGR_OK;
         for (int k = kt - 1; k >= 1; k--) {
             bool fits = true;
             for (int d = 0; d < 3; d++)
@@ -1048,24 +1051,14 @@ int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
             }
         }
         if ((rc = flush())) return rc;
-        if ((rc = single(0))) return rc;
+        // the coarsest values (tail) before the first interpolation
+        MGR_TRY(hipStreamWaitEvent(st, aux->rdone, 0), "tail wait");
     }
-    int waited = -1;  // the correction event the interpolation stream last waited for
     for (int k = kt - 1; k >= 0; k--) {
         const LevelLayout& ly = p.lv[(size_t)k];
         View3 cv = level_view(p, k);
-        hipStream_t sk = (k == 0) ? st : sc;
-        if (k == 0) {
-            // join: the coarser interpolations (sr) and the finest correction
-            MGR_TRY(hipEventRecord(aux->rdone, sc), "join event");
-            MGR_TRY(hipStreamWaitEvent(st, aux->rdone, 0), "join wait");
-            MGR_TRY(hipStreamWaitEvent(st, aux->done[0], 0), "level wait");
-        } else if (cdone[k] != waited) {
-            // each wait costs the interpolation chain a few microseconds even
-            // when the event has completed: one per group of corrections
-            MGR_TRY(hipStreamWaitEvent(sk, aux->done[cdone[k]], 0), "level wait");
-            waited = cdone[k];
-        }
+        hipStream_t sk = st;
+        if (k == 0) MGR_TRY(hipStreamWaitEvent(st, aux->done[0], 0), "join wait");  // the finest correction
         StreamArgs<T> a;
         a.A = src;
         a.Z = ws + p.Zrec[(size_t)k];
