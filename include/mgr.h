@@ -92,14 +92,16 @@ int mgr_decompose(const void* src, void* dst, int dtype, int ndim,
 
 /* Recomposition: the exact inverse of mgr_decompose, coarsest level first
  * (Sec. II-A, overall process). Reads a refactored array from src.
- * The corrections of the level steps (load vector of the stored
- * coefficients and the solves) run on two library-owned streams of the
- * current device, forked from `stream` and joined back into it with events,
- * so the call may be captured into a graph like any other (prepare the
- * problem first with mgr_prepare, which also creates those streams).
- * Recompositions enqueued on different streams share the two streams: their
- * corrections run in enqueue order, and a recomposition must not be
- * enqueued from another thread while a recomposition is being captured. */
+ * The finest level step's correction (load vector of the stored
+ * coefficients and the solves) and the small coarsest levels run on two
+ * library-owned streams of the current device, forked from `stream` and
+ * joined back into it with events, concurrently with the coarser
+ * corrections and interpolations on `stream`; the call may be captured into
+ * a graph like any other (prepare the problem first with mgr_prepare, which
+ * also creates those streams). Recompositions enqueued on different streams
+ * share the two streams: their work there runs in enqueue order, and a
+ * recomposition must not be enqueued from another thread while a
+ * recomposition is being captured. */
 int mgr_recompose(const void* src, void* dst, int dtype, int ndim,
                   const int64_t* shape, const double* const* coords,
                   int nlevels, void* stream);

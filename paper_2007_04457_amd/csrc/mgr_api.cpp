@@ -867,14 +867,13 @@ int run_decompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
     return MGR_OK;
 }
 
-// Three more streams per device for the recomposition (default priority,
-// non-blocking): s0 for the finest level step's correction, s for the
-// coarser ones, sr for the tail and the coarser interpolations; one event per
-// level step (correction done), one for the coarser interpolations and the
-// fork.  The enqueueing is serialised.
+// Two more streams per device for the recomposition (default priority,
+// non-blocking): s0 for the finest level step's correction, sr for the tail;
+// events for the fork, the tail and the finest correction (done[0]).  The
+// enqueueing is serialised.
 constexpr int kMaxLevels = 64;  // above any level count of an int64 extent
 struct AuxStream {
-    hipStream_t s = nullptr, s0 = nullptr, sr = nullptr;
+    hipStream_t s0 = nullptr, sr = nullptr;
     hipEvent_t start = nullptr, rdone = nullptr;
     hipEvent_t done[kMaxLevels] = {};
 };
@@ -887,7 +886,6 @@ void destroy_aux(AuxStream& a)
         if (ev) (void)hipEventDestroy(ev);
     if (a.start) (void)hipEventDestroy(a.start);
     if (a.rdone) (void)hipEventDestroy(a.rdone);
-    if (a.s) (void)hipStreamDestroy(a.s);
     if (a.s0) (void)hipStreamDestroy(a.s0);
     if (a.sr) (void)hipStreamDestroy(a.sr);
     a = AuxStream{};
@@ -900,11 +898,10 @@ hipError_t aux_stream(AuxStream** out)
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     AuxStream& a = g_aux[dev];
-    if (!a.s) {
+    if (!a.sr) {
         // built aside and kept only when complete
         AuxStream n;
-        e = hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.sr, hipStreamNonBlocking);
+        e = hipStreamCreateWithFlags(&n.sr, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&n.s0, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&n.start, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&n.rdone, hipEventDisableTiming);
@@ -925,7 +922,7 @@ bool aux_ready()
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
-    return g_aux[dev].s != nullptr;
+    return g_aux[dev].sr != nullptr;
 }
 
 // Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
