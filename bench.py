@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="sinusoid field only, no other workloads")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 96-field batch against serial calls (for profiling it); prints its own JSON")
+    ap.add_argument("--other-only", action="store_true",
+                    help="only the other plain-method workloads, --steps timed steps each; prints its own JSON "
+                         "(the default run measures them this way, in a child process)")
     ap.add_argument("--dtypes", default="f32,f64", help="comma-separated subset of f32,f64 (default both; "
                                                         "--quick alone means f32)")
     return ap.parse_args()
@@ -313,6 +316,22 @@ def other_workloads(mgr, torch, synth, steps, warmup):
     return out
 
 
+def other_workloads_isolated(steps, warmup):
+    """other_workloads in a child process with a runtime state of its own.
+    In the bench process, after the headline runs' split timings and the
+    copy-kernel runs, the 8193^2 workload's host enqueue time grew about ten
+    times (0.3 -> 3.6 ms per step, removing either earlier part removed the
+    growth), which made its wall-clock rate a measure of the bench's history
+    rather than of the library."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--other-only", "--steps", str(steps),
+           "--warmup", str(warmup), "--no-cpu"]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"other workloads: child process exited with {r.returncode}")
+    return json.loads(r.stdout.strip().splitlines()[-1])["other_workloads"]
+
+
 # HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by the same counters on a copy kernel of known size; valid
 # only while the kernel source matches the one the counters were taken on.
@@ -375,6 +394,10 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": batched_vs_serial(mgr, torch, synth)}), flush=True)
         return
+    if args.other_only:
+        print(json.dumps({"other_workloads": other_workloads(mgr, torch, synth, args.steps, args.warmup)}),
+              flush=True)
+        return
     N = int(np.prod(SHAPE))
     L = mgr.mgr_max_levels(SHAPE)
 
@@ -435,7 +458,7 @@ def main():
     copy_gbps = copy_bandwidth(mgr, torch)
     extra = {}
     if not args.quick:
-        extra["other_workloads"] = other_workloads(mgr, torch, synth, max(3, args.steps // 2), args.warmup)
+        extra["other_workloads"] = other_workloads_isolated(max(3, args.steps // 2), args.warmup)
         print("[bench] batched 96 fields vs serial", file=sys.stderr, flush=True)
         extra["batched"] = batched_vs_serial(mgr, torch, synth)
         print("[bench] adjoint / autograd at 257^3", file=sys.stderr, flush=True)

@@ -928,14 +928,13 @@ bool aux_ready()
 // Recomposition, coarsest level step first: u_k = c_k + Pi (W_{k+1} - z_k).
 // The correction z_k of every level step depends on the stored coefficients
 // alone (its load vector is formed from them), so they are all independent
-// of the coarse-to-fine chain.  Forked from the caller's stream: s0 computes
-// the finest level step's correction, s the coarser ones (coarsest first), sr
-// runs the tail and the coarser interpolations, each waiting only for its own
-// z_k; the caller's stream joins them and runs the finest interpolation.  The
-// latency-bound small levels thus overlap the bandwidth-bound finest
-// correction; the coarser corrections use no whole-CU workgroup (such a
-// workgroup waits until one CU has drained completely of the finest
-// correction's long-lived workgroups).
+// of the coarse-to-fine chain: the finest level step's correction (s0) and
+// the tail (sr) run on streams forked from the caller's, while the caller's
+// stream runs the coarser corrections (sharing launches where they can) and
+// the interpolations.  The latency-bound small levels thus overlap the
+// bandwidth-bound finest correction; the coarser corrections use no whole-CU
+// workgroup (such a workgroup waits until one CU has drained completely of
+// the finest correction's long-lived workgroups).
 template <typename T>
 int run_recompose(const Plan& p, const void* src_, void* dst_, hipStream_t st)
 {
