@@ -142,12 +142,14 @@ def batched_vs_serial(mgr, torch, synth):
     out = {"fields": len(xs), "input_bytes": nbytes, "serial_ms": round(t_serial, 4),
            "serial_GBps": round(nbytes / t_serial / 1e6, 2)}
     want = [mgr.decompose(x) for x in xs]
-    # the autotuner picks the launch form and chunk (model fitted to probe
-    # runs of each form, top three timed); both forms are then timed at the
+    # the autotuner picks the tile geometry, launch form and chunk (model
+    # fitted to probe runs of each, top three timed); both forms are then timed at the
     # best chunk of a plain sweep as well
     tuned_chunk, _, _ = plan.autotune(xs, ys, top_k=3)
     tuned_form, model = plan.tuning()
+    # the sweeps below keep the tile geometry the autotuner chose
     out["autotune"] = {"form": "persistent" if tuned_form else "waves", "chunk": tuned_chunk,
+                       "tile": "wide" if plan.tile() else "narrow",
                        "model_ms_a_perbyte_peritem_perdepthplane": {k: [float(f"{v:.4g}") for v in m]
                                                                      for k, m in model.items()}}
     for mode in ("waves", "persistent"):

@@ -285,22 +285,25 @@ int mgr_batch_plan_create(int nfields, const int* ndim, const int64_t* const* sh
  * (out of place).  Calls on one plan must be ordered on one stream. */
 int mgr_batch_decompose(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream);
 
-/* Autotuner (the model-then-measure search of Sec. III-C): for each launch
- * form (waves, persistent; mgr_batch_set_mode) it times five probe chunk
+/* Autotuner (the model-then-measure search of Sec. III-C): for each tile
+ * geometry of the 3-D streaming items (narrow, wide; mgr_batch_set_tile:
+ * only where a field is 3-D) and each launch form (waves, persistent;
+ * mgr_batch_set_mode) it times five probe chunk
  * lengths (coarse planes per streaming item: 2, 4, 16, 64, 128) on these
  * fields, fits a transaction model time = a + x * bytes + y * items +
  * z * depth to them with non-negative constants (bytes: the streaming items'
  * traffic with their re-read plane halos; items: streaming items; depth: the
  * planes the longest streaming item of each level step streams, summed over
  * the level steps), ranks every chunk length 2..128 by the fitted model and
- * times the best top_k; the plan keeps the fastest (form, chunk) measured,
+ * times the best top_k; the plan keeps the fastest (tile, form, chunk) measured,
  * with the persistent form's poll bound unchanged.  Synchronous; overwrites
  * dst. */
 int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const* dst, void* stream,
                        int top_k);
 
 /* The launch form the plan uses (0 waves, 1 persistent) and the fitted model
- * constants of the last autotune of each form (model: 8 doubles):
+ * constants of the last autotune of each form, on the tile geometry it kept
+ * (model: 8 doubles):
  * model[4 * form + i] = a (ms), x (ms per byte), y (ms per streaming item),
  * z (ms per plane of depth) (zeros for a form not tuned). */
 int mgr_batch_tuning(const mgr_batch_plan* plan, int* persistent, double* model);
@@ -326,6 +329,16 @@ int mgr_batch_set_config(mgr_batch_plan* plan, int chunk);
  *     mgr_batch_check reports it.  The queue words live in the plan, so the
  *     calls (and graph replays) on one plan must be ordered on one stream. */
 int mgr_batch_set_mode(mgr_batch_plan* plan, int persistent, unsigned poll_limit);
+
+/* Tile geometry of the plan's 3-D streaming items (the fine-level step of a
+ * 3-D field): wide = 0 narrow tiles (8 x 30 coarse columns), wide = 1 wide
+ * tiles (8 x 62 coarse columns, two per lane: fewer halo re-reads, fewer
+ * items, more registers).  A new plan starts on the geometry the per-field
+ * calls use for its dtype (narrow FP32, wide FP64).  Results are bit for bit
+ * the same either way; mgr_batch_set_tile rebuilds the work items (wide must
+ * be 0 or 1, else MGR_ERR_ARG); ordering as mgr_batch_set_config. */
+int mgr_batch_tile(const mgr_batch_plan* plan, int* wide);
+int mgr_batch_set_tile(mgr_batch_plan* plan, int wide);
 
 /* Synchronises the device and reports whether the plan's last persistent run
  * aborted (MGR_ERR_HIP, with the work item in mgr_last_error) or not. */

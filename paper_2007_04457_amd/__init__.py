@@ -514,6 +514,18 @@ class BatchPlan:
         mgr_batch_set_mode); poll_limit bounds each dependency wait."""
         _lib.check(_lib.load().mgr_batch_set_mode(self._h, 1 if persistent else 0, int(poll_limit)))
 
+    def tile(self):
+        """True when the 3-D streaming items use the wide tile geometry."""
+        import ctypes
+        w = ctypes.c_int(0)
+        _lib.check(_lib.load().mgr_batch_tile(self._h, ctypes.byref(w)))
+        return bool(w.value)
+
+    def set_tile(self, wide):
+        """Narrow (False) or wide (True) tiles for the 3-D streaming items;
+        rebuilds the work items."""
+        _lib.check(_lib.load().mgr_batch_set_tile(self._h, 1 if wide else 0))
+
     def check(self):
         """Synchronises and raises MgrError if the last persistent run
         aborted."""

@@ -99,6 +99,10 @@ def load():
     lib.mgr_batch_tuning.restype = ctypes.c_int
     lib.mgr_batch_set_mode.argtypes = [vp, ctypes.c_int, ctypes.c_uint]
     lib.mgr_batch_set_mode.restype = ctypes.c_int
+    lib.mgr_batch_tile.argtypes = [vp, i32p]
+    lib.mgr_batch_tile.restype = ctypes.c_int
+    lib.mgr_batch_set_tile.argtypes = [vp, ctypes.c_int]
+    lib.mgr_batch_set_tile.restype = ctypes.c_int
     lib.mgr_batch_check.argtypes = [vp]
     lib.mgr_batch_check.restype = ctypes.c_int
     lib.mgr_batch_queue_check.argtypes = [ctypes.c_int, i32p, ctypes.POINTER(i64p), i32p, ctypes.c_int, ctypes.c_int,

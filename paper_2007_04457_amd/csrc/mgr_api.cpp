@@ -1633,6 +1633,7 @@ struct BatchPlan {
     std::vector<std::pair<int, int>> waves;  // (first item, items) per launch
     int n_items = 0, n_tail = 0;
     int chunk = 8, tuned = 0;
+    int wide = 0;                  // 3-D streaming items on the wide tile geometry
     int64_t bytes = 0;             // input bytes of the batch
     // persistent form (mgr_queue.h): queues (one per XCD), the item at each
     // queue position and each queue's first position, the group of each
@@ -1793,7 +1794,7 @@ int batch_tables(BatchPlan& b, int chunk, BatchTables<T>& out)
             a.write_coarse = (k == 0) ? 1 : 0;
             const bool act0 = a.av.n[0] > 1, act1 = a.av.n[1] > 1;
             int kT1, kT2;
-            level_tiling(act1, (int)sizeof(T), &kT1, &kT2);
+            level_tiling(act1, (int)sizeof(T), b.wide != 0, &kT1, &kT2);
             a.nt1 = act1 ? (int)cdiv(a.fv.n[1], kT1) : 1;
             a.nt2 = (int)cdiv(a.fv.n[2], kT2);
             const int c0 = (int)a.fv.n[0];
@@ -1802,7 +1803,7 @@ int batch_tables(BatchPlan& b, int chunk, BatchTables<T>& out)
             const int sidx = (int)out.sargs.size();
             out.sargs.push_back(a);
             std::vector<BatchItem> s0;
-            const int type = (act0 && act1) ? BI_STREAM3 : act0 ? BI_STREAM2 : BI_STREAM1;
+            const int type = (act0 && act1) ? (b.wide ? BI_STREAM3W : BI_STREAM3) : act0 ? BI_STREAM2 : BI_STREAM1;
             for (int t = 0; t < a.nt1 * a.nt2 * a.nch; t++) s0.push_back(BatchItem{type, sidx, t, 0, f});
             stages.push_back(std::move(s0));
             // correction solves, dimensions last to first
@@ -2055,6 +2056,7 @@ int batch_create(int nfields, const int* ndim, const int64_t* const* shapes, con
     auto b = std::unique_ptr<BatchPlan, void (*)(BatchPlan*)>(new BatchPlan, free_batch);
     b->dtype = dtype;
     b->nfields = nfields;
+    b->wide = (dtype == MGR_F64) ? 1 : 0;  // the per-field launches' geometry
     size_t ws_total = 0;
     const size_t esz = (dtype == MGR_F64) ? 8 : 4;
     hipError_t e = hipGetDevice(&b->device);
@@ -2117,7 +2119,7 @@ BatchTerms batch_terms(const BatchPlan& b, int chunk)
             const double c0 = (double)ly.mc[0];
             const bool act0 = ly.m[0] > 1, act1 = ly.m[1] > 1;
             int kT1, kT2;
-            level_tiling(act1, (int)esz, &kT1, &kT2);
+            level_tiling(act1, (int)esz, b.wide != 0, &kT1, &kT2);
             const double tiles = (act1 ? std::ceil((double)ly.mc[1] / kT1) : 1.0) * std::ceil((double)ly.mc[2] / kT2);
             const double ch = act0 ? std::min<double>(std::max(chunk, 2), c0) : c0;
             const double nch = act0 ? std::ceil(c0 / ch) : 1.0;
@@ -2490,6 +2492,7 @@ int batch_host_items(int nfields, const int* ndim, const int64_t* const* shapes,
     if (chunk < 1 || chunk > kMaxBatchChunk) return fail(MGR_ERR_ARG, "chunk must be 1.." + std::to_string(kMaxBatchChunk));
     b.dtype = dtype;
     b.nfields = nfields;
+    b.wide = (dtype == MGR_F64) ? 1 : 0;  // as a new plan starts
     return dtype == MGR_F64 ? batch_host_items_t<double>(nfields, ndim, shapes, nlevels, chunk, nq, b)
                             : batch_host_items_t<float>(nfields, ndim, shapes, nlevels, chunk, nq, b);
 }
@@ -2983,44 +2986,57 @@ int mgr_batch_autotune(mgr_batch_plan* plan, const void* const* src, void* const
             return MGR_OK;
         };
         double best = 1e300;
-        int best_chunk = b->chunk, best_mode = b->persistent;
+        int best_chunk = b->chunk, best_mode = b->persistent, best_wide = b->wide;
+        double models[2][2][kModelTerms] = {};  // per tile geometry and launch form
         const unsigned limit = b->poll_limit;
-        // both launch forms (waves, persistent), each with its own model
-        for (int mode = 0; mode <= 1 && rc == MGR_OK; mode++) {
-            b->persistent = mode;
-            b->poll_limit = limit;
-            // fit the model to three probe configurations, rank every
-            // candidate by it, then time the best top_k
-            std::vector<BatchTerms> terms;
-            std::vector<double> meas;
-            std::map<int, double> timed_ms;
-            for (int c : probes) {
-                double ms = 0.0;
-                rc = time_chunk(c, &ms);
-                if (rc) break;
-                terms.push_back(batch_terms(*b, c));
-                meas.push_back(ms);
-                timed_ms[c] = ms;
-            }
-            if (rc) break;
-            fit_model(terms, meas, b->model[mode]);
-            std::vector<std::pair<double, int>> ranked;
-            for (int c : cand) ranked.emplace_back(model_ms(b->model[mode], batch_terms(*b, c)), c);
-            std::sort(ranked.begin(), ranked.end());
-            for (int i = 0; i < std::min<int>(top_k, (int)ranked.size()) && rc == MGR_OK; i++) {
-                const int c = ranked[(size_t)i].second;
-                if (timed_ms.count(c)) continue;
-                double ms = 0.0;
-                rc = time_chunk(c, &ms);
-                if (rc == MGR_OK) timed_ms[c] = ms;
-            }
-            for (const auto& kv : timed_ms)
-                if (kv.second < best) {
-                    best = kv.second;
-                    best_chunk = kv.first;
-                    best_mode = mode;
+        // both tile geometries where a field is 3-D (the others do not
+        // depend on it), and both launch forms (waves, persistent), each with
+        // its own model
+        bool any3d = false;
+        for (const auto& pl : b->plans) any3d = any3d || (pl->active[0] && pl->active[1]);
+        const int w0 = any3d ? 0 : b->wide, w1 = any3d ? 1 : b->wide;
+        for (int wide = w0; wide <= w1 && rc == MGR_OK; wide++) {
+            b->wide = wide;
+            for (int mode = 0; mode <= 1 && rc == MGR_OK; mode++) {
+                b->persistent = mode;
+                b->poll_limit = limit;
+                // fit the model to the probe configurations, rank every
+                // candidate by it, then time the best top_k
+                std::vector<BatchTerms> terms;
+                std::vector<double> meas;
+                std::map<int, double> timed_ms;
+                for (int c : probes) {
+                    double ms = 0.0;
+                    rc = time_chunk(c, &ms);
+                    if (rc) break;
+                    terms.push_back(batch_terms(*b, c));
+                    meas.push_back(ms);
+                    timed_ms[c] = ms;
                 }
+                if (rc) break;
+                fit_model(terms, meas, models[wide][mode]);
+                std::vector<std::pair<double, int>> ranked;
+                for (int c : cand) ranked.emplace_back(model_ms(models[wide][mode], batch_terms(*b, c)), c);
+                std::sort(ranked.begin(), ranked.end());
+                for (int i = 0; i < std::min<int>(top_k, (int)ranked.size()) && rc == MGR_OK; i++) {
+                    const int c = ranked[(size_t)i].second;
+                    if (timed_ms.count(c)) continue;
+                    double ms = 0.0;
+                    rc = time_chunk(c, &ms);
+                    if (rc == MGR_OK) timed_ms[c] = ms;
+                }
+                for (const auto& kv : timed_ms)
+                    if (kv.second < best) {
+                        best = kv.second;
+                        best_chunk = kv.first;
+                        best_mode = mode;
+                        best_wide = wide;
+                    }
+            }
         }
+        b->wide = best_wide;
+        for (int m = 0; m < 2; m++)
+            for (int i = 0; i < kModelTerms; i++) b->model[m][i] = models[best_wide][m][i];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         b->persistent = best_mode;
@@ -3064,6 +3080,28 @@ int mgr_batch_set_config(mgr_batch_plan* plan, int chunk)
         if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
         if (chunk < 1 || chunk > kMaxBatchChunk) return fail(MGR_ERR_ARG, "chunk must be 1.." + std::to_string(kMaxBatchChunk));
         return b->dtype == MGR_F64 ? batch_upload<double>(*b, chunk) : batch_upload<float>(*b, chunk);
+    } catch (...) {
+        return fail(MGR_ERR_HIP, "unexpected exception");
+    }
+}
+
+int mgr_batch_tile(const mgr_batch_plan* plan, int* wide)
+{
+    const BatchPlan* b = reinterpret_cast<const BatchPlan*>(plan);
+    if (!b || !wide) return fail(MGR_ERR_ARG, "plan or output is NULL");
+    *wide = b->wide;
+    return MGR_OK;
+}
+
+int mgr_batch_set_tile(mgr_batch_plan* plan, int wide)
+{
+    try {
+        g_err.clear();
+        BatchPlan* b = reinterpret_cast<BatchPlan*>(plan);
+        if (!b) return fail(MGR_ERR_ARG, "plan is NULL");
+        if (wide != 0 && wide != 1) return fail(MGR_ERR_ARG, "wide must be 0 or 1");
+        b->wide = wide;
+        return b->dtype == MGR_F64 ? batch_upload<double>(*b, b->chunk) : batch_upload<float>(*b, b->chunk);
     } catch (...) {
         return fail(MGR_ERR_HIP, "unexpected exception");
     }

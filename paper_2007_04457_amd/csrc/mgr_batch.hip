@@ -18,7 +18,8 @@ namespace {
 
 template <typename T>
 union BatchSmem {
-    LevelSmem<T, true, true, true> lv3;
+    LevelSmem<T, true, true, true, false> lv3;
+    LevelSmem<T, true, true, true, true> lv3w;
     LevelSmem<T, true, false, true> lv2;
     LevelSmem<T, false, false, true> lv1;
     StridedSmem<T> str;
@@ -47,10 +48,12 @@ __device__ __forceinline__ S load_uniform(const S* p)
     return out;
 }
 
-template <typename T, bool kAct0, bool kAct1>
+// kWide: the tile geometry the plan chose (3-D only; the 2-D and 1-D
+// geometry does not depend on it).
+template <typename T, bool kAct0, bool kAct1, bool kWide>
 __device__ __attribute__((noinline)) void exec_stream(const BatchKernelArgs<T>* A, const BatchItem* itp)
 {
-    auto& sm = *reinterpret_cast<LevelSmem<T, kAct0, kAct1, true>*>(batch_lds);
+    auto& sm = *reinterpret_cast<LevelSmem<T, kAct0, kAct1, true, kWide>*>(batch_lds);
     const BatchItem it = load_uniform(itp);
     StreamArgs<T> a = load_uniform(A->sargs + it.args);
     if (!a.A) a.A = load_uniform(A->src + it.field);
@@ -60,16 +63,16 @@ __device__ __attribute__((noinline)) void exec_stream(const BatchKernelArgs<T>* 
     if constexpr (cols_per_lane<T>() == 2) {
         if (unit) {
             if (a.Z)
-                stream_level_tile<T, kAct0, kAct1, true, true, true>(a, it.bx, sm);
+                stream_level_tile<T, kAct0, kAct1, true, true, true, kWide>(a, it.bx, sm);
             else
-                stream_level_tile<T, kAct0, kAct1, true, false, true>(a, it.bx, sm);
+                stream_level_tile<T, kAct0, kAct1, true, false, true, kWide>(a, it.bx, sm);
             return;
         }
     }
     if (a.Z)
-        stream_level_tile<T, kAct0, kAct1, true, true, false>(a, it.bx, sm);
+        stream_level_tile<T, kAct0, kAct1, true, true, false, kWide>(a, it.bx, sm);
     else
-        stream_level_tile<T, kAct0, kAct1, true, false, false>(a, it.bx, sm);
+        stream_level_tile<T, kAct0, kAct1, true, false, false, kWide>(a, it.bx, sm);
 }
 
 template <typename T>
@@ -142,9 +145,10 @@ k_batch(const BatchKernelArgs<T>* __restrict__ A, int first)
 {
     const BatchItem* itp = A->items + first + blockIdx.x;
     switch (itp->type) {
-        case BI_STREAM3: exec_stream<T, true, true>(A, itp); break;
-        case BI_STREAM2: exec_stream<T, true, false>(A, itp); break;
-        case BI_STREAM1: exec_stream<T, false, false>(A, itp); break;
+        case BI_STREAM3: exec_stream<T, true, true, false>(A, itp); break;
+        case BI_STREAM3W: exec_stream<T, true, true, true>(A, itp); break;
+        case BI_STREAM2: exec_stream<T, true, false, false>(A, itp); break;
+        case BI_STREAM1: exec_stream<T, false, false, false>(A, itp); break;
         case BI_ROWS: exec_rows<T>(A, itp); break;
         case BI_STRIDED: exec_strided<T>(A, itp); break;
         case BI_SCATTER: exec_scatter<T>(A, itp); break;
@@ -201,9 +205,10 @@ template <typename T>
 __device__ __forceinline__ void run_item(const BatchKernelArgs<T>* A, const BatchItem* itp)
 {
     switch (itp->type) {
-        case BI_STREAM3: exec_stream<T, true, true>(A, itp); break;
-        case BI_STREAM2: exec_stream<T, true, false>(A, itp); break;
-        case BI_STREAM1: exec_stream<T, false, false>(A, itp); break;
+        case BI_STREAM3: exec_stream<T, true, true, false>(A, itp); break;
+        case BI_STREAM3W: exec_stream<T, true, true, true>(A, itp); break;
+        case BI_STREAM2: exec_stream<T, true, false, false>(A, itp); break;
+        case BI_STREAM1: exec_stream<T, false, false, false>(A, itp); break;
         case BI_ROWS: exec_rows<T>(A, itp); break;
         case BI_STRIDED: exec_strided<T>(A, itp); break;
         case BI_SCATTER: exec_scatter<T>(A, itp); break;

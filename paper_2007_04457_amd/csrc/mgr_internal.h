@@ -170,10 +170,10 @@ hipError_t launch_solve_multi(T* const* F, const View3* fv, int d, const SolveTa
 template <typename T>
 hipError_t launch_stream_adjoint(const T* g, View3 gv, const T* y, const T* G, View3 yv, T* O, View3 ov,
                                  DimTables<T> tb, hipStream_t st);
-// Coarse rows and columns per streaming tile (act1: the problem has a
-// second active dimension; elem_bytes: 4 or 8); workgroup id =
-// (chunk * nt1 + t1) * nt2 + t2.
-void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2);
+// Coarse rows and columns per decomposition tile (act1: the problem has a
+// second active dimension; elem_bytes: 4 or 8; wide: the two-wave-wide 3-D
+// geometry); workgroup id = (chunk * nt1 + t1) * nt2 + t2.
+void level_tiling(bool act1, int elem_bytes, bool wide, int* kT1, int* kT2);
 template <typename T>
 hipError_t launch_stream_recon(StreamArgs<T> a, hipStream_t st);
 
@@ -292,7 +292,7 @@ __device__ __forceinline__ int remap_xcd(int bid, int nb)
 // field.  Items are grouped into waves (level step k, stage s) over all
 // fields; one launch per wave, stream order between waves.
 enum BatchItemType {
-    BI_STREAM3 = 0,  // streaming level tile, 3-D problem
+    BI_STREAM3 = 0,  // streaming level tile, 3-D problem, narrow tile geometry
     BI_STREAM2,      // 2-D problem (m0, 1, m2)
     BI_STREAM1,      // 1-D problem
     BI_ROWS,         // solve along the contiguous dimension, a block of rows
@@ -301,6 +301,7 @@ enum BatchItemType {
     BI_SEPARATORS,
     BI_SEG_FINAL,
     BI_SCATTER,      // coarsest values W_L + z_{L-1} to their nodes (fields without a tail)
+    BI_STREAM3W,     // streaming level tile, 3-D problem, wide tile geometry
     BI_COUNT
 };
 

@@ -133,16 +133,20 @@ hipError_t launch_cfg(StreamArgs<T> a, bool dec, hipStream_t st)
 
 }  // namespace
 
-// Coarse rows and columns of a decomposition tile (for the batch's work items).
-void level_tiling(bool act1, int elem_bytes, int* kT1, int* kT2)
+// Coarse rows and columns of a decomposition tile (for the batch's work
+// items): narrow or wide geometry.
+void level_tiling(bool act1, int elem_bytes, bool wide, int* kT1, int* kT2)
 {
     constexpr int Cf = cols_per_lane<float>(), Cd = cols_per_lane<double>();
-    if (elem_bytes == 4) {
-        *kT1 = act1 ? LevelGeom<true, Cf, wide_tile<float, true>()>::kT1 : LevelGeom<false, Cf, false>::kT1;
-        *kT2 = act1 ? LevelGeom<true, Cf, wide_tile<float, true>()>::kT2 : LevelGeom<false, Cf, false>::kT2;
+    if (!act1) {
+        *kT1 = (elem_bytes == 4) ? LevelGeom<false, Cf, false>::kT1 : LevelGeom<false, Cd, false>::kT1;
+        *kT2 = (elem_bytes == 4) ? LevelGeom<false, Cf, false>::kT2 : LevelGeom<false, Cd, false>::kT2;
+    } else if (elem_bytes == 4) {
+        *kT1 = wide ? LevelGeom<true, Cf, true>::kT1 : LevelGeom<true, Cf, false>::kT1;
+        *kT2 = wide ? LevelGeom<true, Cf, true>::kT2 : LevelGeom<true, Cf, false>::kT2;
     } else {
-        *kT1 = act1 ? LevelGeom<true, Cd, wide_tile<double, true>()>::kT1 : LevelGeom<false, Cd, false>::kT1;
-        *kT2 = act1 ? LevelGeom<true, Cd, wide_tile<double, true>()>::kT2 : LevelGeom<false, Cd, false>::kT2;
+        *kT1 = wide ? LevelGeom<true, Cd, true>::kT1 : LevelGeom<true, Cd, false>::kT1;
+        *kT2 = wide ? LevelGeom<true, Cd, true>::kT2 : LevelGeom<true, Cd, false>::kT2;
     }
 }
 

@@ -146,9 +146,9 @@ __device__ __forceinline__ void buf_store_cols(const T (&v)[N], __amdgpu_buffer_
 // odd columns, so that the dim-2 stencil reads consecutive words; sG: dim-2
 // results [r][GW]; sW0, sK0: dim-0 interpolation weights and stencil rows of
 // the chunk.
-template <typename T, bool kAct0, bool kAct1, bool kDec>
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kWide = wide_tile<T, kDec>()>
 struct alignas(16) LevelSmem {
-    using G = LevelGeom<kAct1, cols_per_lane<T>(), wide_tile<T, kDec>()>;
+    using G = LevelGeom<kAct1, cols_per_lane<T>(), kWide>;
     T sU[kDec ? G::NR * G::NCW : 1];
     T sC[G::OB + G::NR * G::H];
     T sG[G::NR * G::GW];
@@ -161,12 +161,14 @@ struct alignas(16) LevelSmem {
 // per-level launch and by the batched kernel.  kU: the input (and, when
 // decomposing, the coefficient output) has unit column stride, so a lane's
 // columns move in one access.
-template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU>
+// kWide: the tile geometry (defaults to the per-level launch's; the batch
+// chooses it per plan).
+template <typename T, bool kAct0, bool kAct1, bool kDec, bool kZ, bool kU, bool kWide = wide_tile<T, kDec>()>
 __device__ __forceinline__ void stream_level_tile(const StreamArgs<T>& a, int bid,
-                                                  LevelSmem<T, kAct0, kAct1, kDec>& sm)
+                                                  LevelSmem<T, kAct0, kAct1, kDec, kWide>& sm)
 {
     constexpr int CPL = cols_per_lane<T>();
-    using G = LevelGeom<kAct1, CPL, wide_tile<T, kDec>()>;
+    using G = LevelGeom<kAct1, CPL, kWide>;
     constexpr int NR = G::NR, NCW = G::NCW, NRW = G::NRW, RW = G::RW, H = G::H, GW = G::GW;
     constexpr int kT1 = G::kT1, kT2 = G::kT2, OB = G::OB;
     constexpr int NGP = (NR + (kThreads / GW) - 1) / (kThreads / GW);  // dim-2 passes

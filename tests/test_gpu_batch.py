@@ -119,7 +119,7 @@ def test_batch_config_and_autotune():
     assert chunk in (2, 4, 8, 16, 32, 64, 128) and launches > 1 and items > 0
     # the model constants were fitted to timed probe runs of both launch forms
     form, model = plan.tuning()
-    assert form in (0, 1)
+    assert form in (0, 1) and plan.tile() in (False, True)
     for m in (model["waves"], model["persistent"]):
         assert len(m) == 4 and all(v >= 0.0 for v in m) and any(v != 0.0 for v in m)
     ys = plan.decompose(xs)
@@ -225,6 +225,34 @@ def test_batch_full_workload_96_fields():
         ref = oracle.decompose(xd)
         err = float(np.max(np.abs(ys[i].double().cpu().numpy() - ref))) / float(np.max(np.abs(xd)))
         assert err <= TOL[torch.float32], (i, shapes[i], err)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_batch_tile_geometry(dtype):
+    """Both tile geometries of the 3-D streaming items (a tuned parameter)
+    give the per-field results bit for bit, in both launch forms; the
+    setting is kept across set_config and rejected outside 0/1."""
+    xs, coords = make_fields(MIXED, dtype, 540)
+    plan = mgr.BatchPlan([x.shape for x in xs], dtype, coords)
+    assert plan.tile() == (dtype == torch.float64)
+    want = [mgr.decompose(x, c) for x, c in zip(xs, coords)]
+    for wide in (True, False):
+        plan.set_tile(wide)
+        assert plan.tile() == wide
+        for persistent in (False, True):
+            plan.set_mode(persistent)
+            for chunk in (4, 32):
+                print(f"\n[batch-tile] {dtype} wide {wide} persistent {persistent} chunk {chunk}", flush=True)
+                plan.set_config(chunk)
+                assert plan.tile() == wide
+                ys = plan.decompose(xs)
+                plan.check()
+                for i in range(len(xs)):
+                    assert torch.equal(ys[i], want[i]), (wide, persistent, chunk, i, MIXED[i])
+    with pytest.raises(mgr.MgrError):
+        mgr._lib.check(mgr._lib.load().mgr_batch_set_tile(plan._h, 2))
+    assert plan.tile() is False  # unchanged by the rejected call
     plan.close()
 
 
