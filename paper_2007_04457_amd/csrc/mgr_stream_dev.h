@@ -37,12 +37,14 @@ int resident_per_cu(K kern, int& cache)
 // tile width.
 //  3-D: a workgroup owns kT1 = 8 coarse rows x kT2 = (64 CW CPL - 3) / 2
 //       coarse columns; its staged region is 19 fine rows x 2 kT2 + 3
-//       columns.  Narrow (FP32): CW = 1 wave per staged row, kT2 = 30 (rows
-//       r = wave, wave + 4, ...).  Wide (FP64): CW = 2 waves side by side
+//       columns.  Narrow: CW = 1 wave per staged row, kT2 = 30 (rows
+//       r = wave, wave + 4, ...).  Wide: CW = 2 waves side by side
 //       per row, kT2 = 62 (rows r = wave / 2, wave / 2 + 2, ...): half as
 //       many tile edges per row (cache lines split between two tiles' stores)
 //       and a slightly smaller halo, for twice the rows per wave, which only
-//       the two-plane register ring leaves room for.
+//       the two-plane register ring leaves room for.  The per-field
+//       launches take the geometry wide_tile gives; the batch's 3-D items
+//       take either, as its autotuner chose.
 //  2-D (m0, 1, m2) and 1-D (1, 1, m2): one staged row, four waves side by
 //       side (kT2 = (256 CPL - 3) / 2 = 126 at CPL = 1).
 template <bool kAct1, int CPL, bool kWide>
